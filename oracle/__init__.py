@@ -1,0 +1,35 @@
+"""FP64 CPU oracle for the FDAS correlation step (test infrastructure only).
+
+This package is the checker, not the product. Only ``tests/``, the smoke
+check in ``__graft_entry__`` and the ``cpu_baseline`` leg of ``bench.py``
+may import it. It shares no code with the HIP path: nothing here imports the
+package ``paper_1711_10855_amd`` and nothing there imports this package.
+
+What it computes (paper: Adamek, Dimoudi, Giles & Armour, "Improved
+Acceleration of the GPU Fourier Domain Acceleration Search Algorithm"):
+
+* ``templates``  -- the predicted, normalised Fourier response H of a signal
+  with constant frequency derivative (Section 1, the response named before
+  eq. 2), in the closed form derived from its defining integral.
+* ``correlate``  -- the matched-filter sum of eq. 2 (Section 1) evaluated
+  directly, and, independently, the same result by overlap-and-save
+  (Section 2) with naive DFT matrices built from eq. 3.
+"""
+
+from .templates import (  # noqa: F401
+    z_grid,
+    response_g,
+    template_h,
+    templates64,
+    response_g_quadrature,
+    response_g_mpmath,
+)
+from .correlate import (  # noqa: F401
+    correlate_direct,
+    plane_direct,
+    plane_points,
+    plane_ols_naive,
+    correlate_bruteforce,
+    correlate_at,
+    bank_natural,
+)
