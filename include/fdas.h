@@ -1,0 +1,179 @@
+/*
+ * fdas.h -- C ABI of the FDAS correlation step on AMD Instinct MI355X (gfx950).
+ *
+ * What it computes (Adamek, Dimoudi, Giles & Armour, "Improved Acceleration
+ * of the GPU Fourier Domain Acceleration Search Algorithm"):
+ *
+ *   For every trial drift z_i = -zmax + i*dz, i in [0, nz), nz = 2*zmax/dz + 1
+ *   (z is the number of bins the signal frequency drifts over the observation,
+ *   Section 1, eq. 1), and every bin r in [0, nbins):
+ *
+ *     B_i(r) = sum_{q=-m/2}^{m/2} A[r+q] * conj(H_{z_i}(q))      (Section 1, eq. 2)
+ *     power[i*ld + r] = |B_i(r)|^2
+ *
+ *   A is the complex spectrum (zero outside [0, nbins)); H_z(q) is the
+ *   predicted, normalised Fourier response of a constant-frequency-derivative
+ *   signal (Section 1): H_z(q) = exp(-i pi q) * integral_{-1/2}^{1/2}
+ *   exp(i pi (z s^2 - 2 q s)) ds, evaluated in FP64 through Fresnel integrals.
+ *   The sum is computed by overlap-and-save (Section 2): segments of L bins,
+ *   a forward FFT (eq. 3 sign convention) held in on-chip memory, one
+ *   pointwise product and one inverse FFT per template (Section 3), discard of
+ *   the m wrapped outputs, and |.|^2 written straight to device memory.
+ *
+ * Conventions for every entry point:
+ *   - Sample buffers (spectrum, power, templates, bank copies) are DEVICE
+ *     pointers owned by the caller; structs and status are host memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Work is stream-ordered and asynchronous; buffers must stay live until
+ *     the stream has synchronised.
+ *   - Every call validates its arguments on the host before any HIP call and
+ *     returns a status code; nothing is thrown across the ABI. Detail for the
+ *     last failure on the calling thread is in fdas_last_error().
+ *   - A plan may be used from one stream at a time (it owns scratch state).
+ *   - Results are bitwise deterministic for a fixed plan and input.
+ */
+#ifndef FDAS_H
+#define FDAS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------- */
+#define FDAS_OK 0
+#define FDAS_ERR_INVALID (-1)     /* bad argument (checked before device work) */
+#define FDAS_ERR_UNSUPPORTED (-2) /* valid but not compiled in (e.g. seg_len)   */
+#define FDAS_ERR_NOMEM (-3)       /* a device or host allocation failed         */
+#define FDAS_ERR_DEVICE (-4)      /* a HIP runtime call failed                  */
+
+/* ---- precisions ---------------------------------------------------------- */
+#define FDAS_FP32 0        /* FP32 storage and FFTs, FP32 output             */
+#define FDAS_MIXED_FP16 1  /* FP16 storage, MFMA DFT stages, FP32 accumulate */
+#define FDAS_MIXED_BF16 2  /* BF16 storage, MFMA DFT stages, FP32 accumulate */
+
+/* ---- flags ----------------------------------------------------------------- */
+#define FDAS_FLAG_SPLIT 1u    /* mixed: hi+lo split products (3 MFMA per stage) */
+#define FDAS_FLAG_AUTOTUNE 2u /* fdas_plan: time the candidate kernels, keep best */
+
+/* Filter-bank parameters.
+ *   zmax, dz  : z grid z_i = -zmax + i*dz; zmax >= 0, dz > 0, 2*zmax/dz an
+ *               integer within 1e-9.
+ *   m         : even, >= 2; taps q in [-m/2, m/2] (m + 1 bins, eq. 2).
+ *               0 selects the default nextpow2(2*zmax + 32), at least 8.
+ *   seg_len   : overlap-and-save segment (FFT) length L, a power of two in
+ *               [256, 16384] with L > m. 0 selects the default (from the
+ *               autotune cache if one is loaded, else min 8*m clamped).
+ *   precision : FDAS_FP32 / FDAS_MIXED_FP16 / FDAS_MIXED_BF16.
+ *   flags     : FDAS_FLAG_* bits.                                           */
+typedef struct {
+  double zmax;
+  double dz;
+  int m;
+  int seg_len;
+  int precision;
+  unsigned flags;
+} fdas_params;
+
+/* One series of a batch (fdas_convolve_batch).
+ *   spectrum : device complex64 [nbins] (interleaved re, im; 8-byte aligned).
+ *   nbins    : >= 1.
+ *   zmax     : this series' zmax; <= the plan's zmax and on its grid
+ *              ((plan.zmax - zmax)/dz an integer). Its plane has
+ *              nz_s = 2*zmax/dz + 1 rows, row j <-> z = -zmax + j*dz.
+ *   power    : device float [nz_s][ld], ld >= nbins.                        */
+typedef struct {
+  const void *spectrum;
+  int64_t nbins;
+  double zmax;
+  float *power;
+  int64_t ld;
+} fdas_series;
+
+/* What a plan resolved to (fdas_plan_get_info). */
+typedef struct {
+  int nz;              /* rows of the plane                                  */
+  int m;               /* window (taps -m/2..m/2)                            */
+  int seg_len;         /* L                                                  */
+  int valid;           /* U = L - m outputs kept per segment                 */
+  int precision;
+  unsigned flags;
+  int threads;         /* threads per segment in the hot kernel              */
+  int templates_per_block;
+  int segments_per_block;
+  size_t bank_bytes;   /* device bytes of the Fourier-domain template bank   */
+  double plan_ms;      /* wall time of fdas_plan (templates + bank)          */
+  char kernel[64];     /* name of the selected hot-kernel variant            */
+} fdas_plan_info;
+
+typedef struct fdas_plan_s *fdas_plan_t;
+
+/* Number of plane rows nz = 2*zmax/dz + 1 for valid params, else a negative
+ * status. Host only; never touches the device.                              */
+int fdas_plane_rows(const fdas_params *p);
+
+/* Fill defaults (m, seg_len) and validate; *out receives the resolved
+ * parameters. Host only. Returns FDAS_OK, FDAS_ERR_INVALID or
+ * FDAS_ERR_UNSUPPORTED.                                                      */
+int fdas_resolve_params(const fdas_params *in, fdas_params *out);
+
+/* Template generation (Section 1, the predicted normalised response H used in
+ * eq. 2), in FP64 on the device.
+ *   templates : device complex128 [nz][m+1], element [i][j] = H_{z_i}(j - m/2),
+ *               or NULL to only query the size.
+ *   bytes     : in/out. On return holds the required size in bytes. When
+ *               templates != NULL, *bytes on entry must be >= that size.
+ * Parameters are resolved as in fdas_resolve_params. The call is
+ * asynchronous on `stream`.                                                  */
+int fdas_make_templates(const fdas_params *p, void *templates, size_t *bytes,
+                        void *stream);
+
+/* Build a plan on `device`: generates the templates (FP64), transforms them
+ * to the Fourier-domain bank T_i[k] = conj(FFT_L(h_i))[k] / L with
+ * h_i[q mod L] = H_{z_i}(q) (FP64, then rounded to the storage precision and
+ * laid out in the hot kernel's register order), builds twiddle tables, and
+ * picks the kernel variant (autotuned with FDAS_FLAG_AUTOTUNE). Synchronises
+ * `stream` before returning. *out is NULL on failure.                        */
+int fdas_plan(fdas_plan_t *out, const fdas_params *p, int device, void *stream);
+
+/* Report the resolved configuration of a plan.                              */
+int fdas_plan_get_info(fdas_plan_t plan, fdas_plan_info *info);
+
+/* Copy the plan's bank, in natural frequency order, as complex64 [nz][L]
+ * (FP32 plans: exactly the stored values; mixed plans: hi + lo widened to
+ * FP32) into device memory `dst` of at least nz*L*8 bytes. For testing.    */
+int fdas_plan_bank(fdas_plan_t plan, void *dst, size_t bytes, void *stream);
+
+/* The hot path: power[i*ld + r] = |B_i(r)|^2 for one spectrum.
+ *   spectrum : device complex64 [nbins]; nbins >= 1.
+ *   power    : device float [nz][ld], ld >= nbins; fully overwritten in
+ *              columns [0, nbins) of every row.
+ * Asynchronous on `stream`; launches only kernels (no allocation, no copy). */
+int fdas_convolve(fdas_plan_t plan, const void *spectrum, int64_t nbins,
+                  float *power, int64_t ld, void *stream);
+
+/* Batched hot path: one persistent launch over every (series, segment,
+ * template group) work item, largest series first, items taken from a device
+ * counter. Each series uses the central nz_s rows of the plan's bank. The
+ * launch is captured once into a HIP graph per distinct batch shape and
+ * replayed. `series` is host memory with nseries >= 1 entries.              */
+int fdas_convolve_batch(fdas_plan_t plan, const fdas_series *series,
+                        int nseries, void *stream);
+
+/* Release a plan and everything it owns. NULL is allowed (returns FDAS_OK).
+ * Synchronises the device the plan lives on.                                */
+int fdas_destroy(fdas_plan_t plan);
+
+/* Static description of a status code.                                      */
+const char *fdas_status_string(int status);
+
+/* Detail of the last failure on the calling thread ("" if none).            */
+const char *fdas_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FDAS_H */

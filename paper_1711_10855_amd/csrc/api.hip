@@ -1,0 +1,224 @@
+// Host side of the C ABI declared in include/fdas.h: argument validation
+// (always before any HIP call), plan construction and kernel dispatch.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "fdas.h"
+#include "ols_variants.hpp"
+#include "plan.hpp"
+
+namespace fdas {
+
+static thread_local std::string g_last_error;
+
+int set_error(int status, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return status;
+}
+
+int hip_error(hipError_t e, const char *what) {
+  return set_error(FDAS_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+static int next_pow2(double v) {
+  int p = 1;
+  while (p < v && p < (1 << 30)) p <<= 1;
+  return p;
+}
+
+// Validate the z grid; returns nz or a negative status.
+static int validate_grid(double zmax, double dz) {
+  if (!std::isfinite(zmax) || !std::isfinite(dz) || zmax < 0.0 || dz <= 0.0)
+    return set_error(FDAS_ERR_INVALID, "need finite zmax >= 0 and dz > 0 (zmax=%g dz=%g)", zmax, dz);
+  const double span = 2.0 * zmax / dz;
+  if (span > 1e6) return set_error(FDAS_ERR_INVALID, "2*zmax/dz = %g is too large", span);
+  const double n = std::nearbyint(span);
+  if (std::fabs(span - n) > 1e-9)
+    return set_error(FDAS_ERR_INVALID, "2*zmax/dz = %.12g is not an integer", span);
+  return (int)n + 1;
+}
+
+int resolve_params(const fdas_params *in, fdas_params *out, int *nz_out) {
+  if (!in || !out) return set_error(FDAS_ERR_INVALID, "null params pointer");
+  fdas_params p = *in;
+  const int nz = validate_grid(p.zmax, p.dz);
+  if (nz < 0) return nz;
+  if (p.flags & ~(FDAS_FLAG_SPLIT | FDAS_FLAG_AUTOTUNE))
+    return set_error(FDAS_ERR_INVALID, "unknown flag bits 0x%x", p.flags);
+  if (p.precision != FDAS_FP32 && p.precision != FDAS_MIXED_FP16 &&
+      p.precision != FDAS_MIXED_BF16)
+    return set_error(FDAS_ERR_INVALID, "unknown precision %d", p.precision);
+  if (p.m == 0) {
+    p.m = next_pow2(2.0 * p.zmax + 32.0);
+    if (p.m < 8) p.m = 8;
+  }
+  if (p.m < 2 || (p.m & 1)) return set_error(FDAS_ERR_INVALID, "m must be even and >= 2 (m=%d)", p.m);
+  if (p.m > 8192) return set_error(FDAS_ERR_UNSUPPORTED, "m=%d exceeds the largest segment", p.m);
+  if (p.seg_len == 0) p.seg_len = default_seg_len(p.m, nz, p.precision);
+  if (p.seg_len < 0) return set_error(FDAS_ERR_INVALID, "seg_len must be >= 0");
+  if (p.seg_len <= p.m)
+    return set_error(FDAS_ERR_INVALID, "seg_len (%d) must exceed m (%d)", p.seg_len, p.m);
+  if ((p.seg_len & (p.seg_len - 1)) || p.seg_len < 256 || p.seg_len > 16384)
+    return set_error(FDAS_ERR_UNSUPPORTED, "seg_len %d: compiled lengths are powers of two in [256, 16384]",
+                     p.seg_len);
+  if (p.precision != FDAS_FP32 && !mixed_supported(p.seg_len))
+    return set_error(FDAS_ERR_UNSUPPORTED, "precision %d is not available for seg_len %d",
+                     p.precision, p.seg_len);
+  *out = p;
+  if (nz_out) *nz_out = nz;
+  return FDAS_OK;
+}
+
+int default_seg_len(int m, int nz, int precision) {
+  (void)nz;
+  (void)precision;
+  int L = next_pow2(8.0 * m);
+  if (L < 256) L = 256;
+  if (L > 16384) L = 16384;
+  return L;
+}
+
+// Device guard: makes `dev` current for the scope and restores the caller's.
+struct DeviceGuard {
+  int prev = -1;
+  hipError_t err = hipSuccess;
+  explicit DeviceGuard(int dev) {
+    err = hipGetDevice(&prev);
+    if (err == hipSuccess && prev != dev) err = hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+}  // namespace fdas
+
+using namespace fdas;
+
+extern "C" {
+
+const char *fdas_status_string(int status) {
+  switch (status) {
+    case FDAS_OK: return "ok";
+    case FDAS_ERR_INVALID: return "invalid argument";
+    case FDAS_ERR_UNSUPPORTED: return "unsupported configuration";
+    case FDAS_ERR_NOMEM: return "out of memory";
+    case FDAS_ERR_DEVICE: return "device error";
+    default: return "unknown status";
+  }
+}
+
+const char *fdas_last_error(void) { return g_last_error.c_str(); }
+
+int fdas_plane_rows(const fdas_params *p) {
+  if (!p) return set_error(FDAS_ERR_INVALID, "null params pointer");
+  return validate_grid(p->zmax, p->dz);
+}
+
+int fdas_resolve_params(const fdas_params *in, fdas_params *out) {
+  return resolve_params(in, out, nullptr);
+}
+
+int fdas_make_templates(const fdas_params *p, void *templates, size_t *bytes, void *stream) {
+  fdas_params r;
+  int nz = 0;
+  int st = resolve_params(p, &r, &nz);
+  if (st) return st;
+  if (!bytes) return set_error(FDAS_ERR_INVALID, "null bytes pointer");
+  const size_t need = (size_t)nz * (size_t)(r.m + 1) * 16;
+  if (!templates) {
+    *bytes = need;
+    return FDAS_OK;
+  }
+  if (*bytes < need) {
+    const size_t have = *bytes;
+    *bytes = need;
+    return set_error(FDAS_ERR_INVALID, "templates buffer holds %zu bytes, need %zu", have, need);
+  }
+  *bytes = need;
+  hipError_t e = launch_templates(templates, nz, r.m, r.zmax, r.dz, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_error(e, "template kernel launch");
+  return FDAS_OK;
+}
+
+int fdas_plan(fdas_plan_t *out, const fdas_params *p, int device, void *stream) {
+  if (!out) return set_error(FDAS_ERR_INVALID, "null plan output pointer");
+  *out = nullptr;
+  fdas_params r;
+  int nz = 0;
+  int st = resolve_params(p, &r, &nz);
+  if (st) return st;
+  if (device < 0) return set_error(FDAS_ERR_INVALID, "device %d < 0", device);
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess) return hip_error(e, "hipGetDeviceCount");
+  if (device >= ndev) return set_error(FDAS_ERR_INVALID, "device %d of %d", device, ndev);
+  DeviceGuard guard(device);
+  if (guard.err != hipSuccess) return hip_error(guard.err, "hipSetDevice");
+  return build_plan(out, r, nz, device, (hipStream_t)stream);
+}
+
+int fdas_plan_get_info(fdas_plan_t plan, fdas_plan_info *info) {
+  if (!plan || !info) return set_error(FDAS_ERR_INVALID, "null plan or info pointer");
+  plan_info(plan, info);
+  return FDAS_OK;
+}
+
+int fdas_plan_bank(fdas_plan_t plan, void *dst, size_t bytes, void *stream) {
+  if (!plan || !dst) return set_error(FDAS_ERR_INVALID, "null plan or destination");
+  const size_t need = (size_t)plan_rows(plan) * (size_t)plan_seg_len(plan) * 8;
+  if (bytes < need) return set_error(FDAS_ERR_INVALID, "destination holds %zu bytes, need %zu", bytes, need);
+  DeviceGuard guard(plan_device(plan));
+  if (guard.err != hipSuccess) return hip_error(guard.err, "hipSetDevice");
+  return plan_bank_natural(plan, dst, (hipStream_t)stream);
+}
+
+int fdas_convolve(fdas_plan_t plan, const void *spectrum, int64_t nbins, float *power, int64_t ld,
+                  void *stream) {
+  if (!plan) return set_error(FDAS_ERR_INVALID, "null plan");
+  if (!spectrum || !power) return set_error(FDAS_ERR_INVALID, "null spectrum or power pointer");
+  if (nbins < 1) return set_error(FDAS_ERR_INVALID, "nbins must be >= 1 (got %lld)", (long long)nbins);
+  if (ld < nbins) return set_error(FDAS_ERR_INVALID, "ld (%lld) < nbins (%lld)", (long long)ld, (long long)nbins);
+  if ((reinterpret_cast<uintptr_t>(spectrum) & 7) || (reinterpret_cast<uintptr_t>(power) & 3))
+    return set_error(FDAS_ERR_INVALID, "misaligned spectrum or power pointer");
+  DeviceGuard guard(plan_device(plan));
+  if (guard.err != hipSuccess) return hip_error(guard.err, "hipSetDevice");
+  return plan_convolve(plan, spectrum, nbins, power, ld, (hipStream_t)stream);
+}
+
+int fdas_convolve_batch(fdas_plan_t plan, const fdas_series *series, int nseries, void *stream) {
+  if (!plan) return set_error(FDAS_ERR_INVALID, "null plan");
+  if (!series || nseries < 1) return set_error(FDAS_ERR_INVALID, "need nseries >= 1 and a series array");
+  for (int i = 0; i < nseries; ++i) {
+    const fdas_series &s = series[i];
+    if (!s.spectrum || !s.power) return set_error(FDAS_ERR_INVALID, "series %d: null pointer", i);
+    if (s.nbins < 1) return set_error(FDAS_ERR_INVALID, "series %d: nbins < 1", i);
+    if (s.ld < s.nbins) return set_error(FDAS_ERR_INVALID, "series %d: ld < nbins", i);
+    if ((reinterpret_cast<uintptr_t>(s.spectrum) & 7) || (reinterpret_cast<uintptr_t>(s.power) & 3))
+      return set_error(FDAS_ERR_INVALID, "series %d: misaligned pointer", i);
+  }
+  DeviceGuard guard(plan_device(plan));
+  if (guard.err != hipSuccess) return hip_error(guard.err, "hipSetDevice");
+  return plan_convolve_batch(plan, series, nseries, (hipStream_t)stream);
+}
+
+int fdas_destroy(fdas_plan_t plan) {
+  if (!plan) return FDAS_OK;
+  DeviceGuard guard(plan_device(plan));
+  return destroy_plan(plan);
+}
+
+}  // extern "C"

@@ -1,0 +1,153 @@
+// In-register complex DFT kernels of radix 2, 4, 8 and 16 for gfx950.
+//
+// The discrete Fourier transform follows eq. 3 of the paper (Section 2):
+// X_k = sum_n x_n exp(-i 2 pi n k / N). DIR = -1 is that forward transform,
+// DIR = +1 its unnormalised inverse. Inputs and outputs are in natural order
+// in a register array; radix 8 and 16 are built from radix-4 butterflies with
+// their internal twiddles as compile-time constants, so trivial factors
+// (1, -i, (1 -/+ i)/sqrt 2) cost adds only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace fdas {
+
+struct __attribute__((aligned(8))) c32 {
+  float x, y;
+};
+
+__device__ __forceinline__ c32 cadd(c32 a, c32 b) { return {a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ c32 csub(c32 a, c32 b) { return {a.x - b.x, a.y - b.y}; }
+__device__ __forceinline__ c32 cmul(c32 a, c32 b) {
+  return {__builtin_fmaf(a.x, b.x, -a.y * b.y), __builtin_fmaf(a.x, b.y, a.y * b.x)};
+}
+// a * conj(b)
+__device__ __forceinline__ c32 cmulc(c32 a, c32 b) {
+  return {__builtin_fmaf(a.x, b.x, a.y * b.y), __builtin_fmaf(a.y, b.x, -a.x * b.y)};
+}
+
+// Multiply by exp(DIR * i pi / 2): -i for the forward transform, +i inverse.
+template <int DIR>
+__device__ __forceinline__ c32 rot90(c32 v) {
+  if constexpr (DIR < 0) return {v.y, -v.x};
+  else return {-v.y, v.x};
+}
+
+// Multiply by exp(DIR * i 2 pi J / 16) for a compile-time J in [0, 16).
+template <int DIR, int J>
+__device__ __forceinline__ c32 tw16(c32 v) {
+  constexpr float C1 = 0.92387953251128675613f;  // cos(pi/8)
+  constexpr float S1 = 0.38268343236508977173f;  // sin(pi/8)
+  constexpr float H = 0.70710678118654752440f;   // 1/sqrt(2)
+  constexpr int j = J & 15;
+  if constexpr (j == 0) {
+    return v;
+  } else if constexpr (j == 4) {
+    return rot90<DIR>(v);
+  } else if constexpr (j == 8) {
+    return {-v.x, -v.y};
+  } else if constexpr (j == 12) {
+    return rot90<-DIR>(v);
+  } else if constexpr (j == 2 || j == 6 || j == 10 || j == 14) {
+    // (1 -/+ i)/sqrt2 rotated by multiples of 90 degrees
+    c32 w;
+    if constexpr (DIR < 0) w = {(v.x + v.y) * H, (v.y - v.x) * H};  // * (1 - i)/sqrt2
+    else w = {(v.x - v.y) * H, (v.x + v.y) * H};                   // * (1 + i)/sqrt2
+    if constexpr (j == 2) return w;
+    else if constexpr (j == 6) return rot90<DIR>(w);
+    else if constexpr (j == 10) return {-w.x, -w.y};
+    else return rot90<-DIR>(w);
+  } else {
+    // odd j: exp(DIR i 2 pi j / 16) = cos(pi j/8) + DIR i sin(pi j/8)
+    constexpr int q = j & 3;       // 1 or 3 within the quadrant
+    constexpr int quad = j >> 2;   // number of 90 degree turns
+    constexpr float c = (q == 1) ? C1 : S1;
+    constexpr float s = (q == 1) ? S1 : C1;
+    constexpr float sd = (DIR < 0) ? -s : s;
+    c32 w = {__builtin_fmaf(v.x, c, -v.y * sd), __builtin_fmaf(v.x, sd, v.y * c)};
+    if constexpr (quad == 0) return w;
+    else if constexpr (quad == 1) return rot90<DIR>(w);
+    else if constexpr (quad == 2) return {-w.x, -w.y};
+    else return rot90<-DIR>(w);
+  }
+}
+
+template <int DIR>
+__device__ __forceinline__ void dft2(c32 &a, c32 &b) {
+  c32 t = a;
+  a = cadd(t, b);
+  b = csub(t, b);
+}
+
+template <int DIR>
+__device__ __forceinline__ void dft4(c32 &a, c32 &b, c32 &c, c32 &d) {
+  c32 t0 = cadd(a, c), t1 = csub(a, c);
+  c32 t2 = cadd(b, d), t3 = rot90<DIR>(csub(b, d));
+  a = cadd(t0, t2);
+  c = csub(t0, t2);
+  b = cadd(t1, t3);
+  d = csub(t1, t3);
+}
+
+// v[0..8) natural order in and out.
+template <int DIR>
+__device__ __forceinline__ void dft8(c32 *v) {
+  c32 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  c32 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+  dft4<DIR>(e0, e1, e2, e3);
+  dft4<DIR>(o0, o1, o2, o3);
+  o1 = tw16<DIR, 2>(o1);
+  o2 = tw16<DIR, 4>(o2);
+  o3 = tw16<DIR, 6>(o3);
+  v[0] = cadd(e0, o0);
+  v[4] = csub(e0, o0);
+  v[1] = cadd(e1, o1);
+  v[5] = csub(e1, o1);
+  v[2] = cadd(e2, o2);
+  v[6] = csub(e2, o2);
+  v[3] = cadd(e3, o3);
+  v[7] = csub(e3, o3);
+}
+
+// v[0..16) natural order in and out: 4 x 4 decomposition n = 4 n1 + n2,
+// k = k1 + 4 k2, internal twiddle W16^(n2 k1).
+template <int DIR>
+__device__ __forceinline__ void dft16(c32 *v) {
+  dft4<DIR>(v[0], v[4], v[8], v[12]);
+  dft4<DIR>(v[1], v[5], v[9], v[13]);
+  dft4<DIR>(v[2], v[6], v[10], v[14]);
+  dft4<DIR>(v[3], v[7], v[11], v[15]);
+  // after the first pass v[4*k1 + n2] holds Y[n2][k1]
+  v[5] = tw16<DIR, 1>(v[5]);
+  v[9] = tw16<DIR, 2>(v[9]);
+  v[13] = tw16<DIR, 3>(v[13]);
+  v[6] = tw16<DIR, 2>(v[6]);
+  v[10] = tw16<DIR, 4>(v[10]);
+  v[14] = tw16<DIR, 6>(v[14]);
+  v[7] = tw16<DIR, 3>(v[7]);
+  v[11] = tw16<DIR, 6>(v[11]);
+  v[15] = tw16<DIR, 9>(v[15]);
+  dft4<DIR>(v[0], v[1], v[2], v[3]);
+  dft4<DIR>(v[4], v[5], v[6], v[7]);
+  dft4<DIR>(v[8], v[9], v[10], v[11]);
+  dft4<DIR>(v[12], v[13], v[14], v[15]);
+  // now v[4*k1 + k2] holds X[k1 + 4 k2]; transpose to natural order
+  c32 t;
+  t = v[1]; v[1] = v[4]; v[4] = t;
+  t = v[2]; v[2] = v[8]; v[8] = t;
+  t = v[3]; v[3] = v[12]; v[12] = t;
+  t = v[6]; v[6] = v[9]; v[9] = t;
+  t = v[7]; v[7] = v[13]; v[13] = t;
+  t = v[11]; v[11] = v[14]; v[14] = t;
+}
+
+template <int DIR, int R>
+__device__ __forceinline__ void dft(c32 *v) {
+  static_assert(R == 2 || R == 4 || R == 8 || R == 16, "radix");
+  if constexpr (R == 2) dft2<DIR>(v[0], v[1]);
+  else if constexpr (R == 4) dft4<DIR>(v[0], v[1], v[2], v[3]);
+  else if constexpr (R == 8) dft8<DIR>(v);
+  else dft16<DIR>(v);
+}
+
+}  // namespace fdas

@@ -1,0 +1,273 @@
+// Fused FP32 overlap-and-save correlation kernel for gfx950.
+//
+// One work unit = (segment s, group of templates). For its segment the kernel
+//   1. loads x_j = A[s U - m/2 + j], j in [0, L), zero outside [0, nbins)
+//      (the overlap-and-save segment, Section 2), coalesced;
+//   2. runs the forward FFT (eq. 3 sign) once, decimation in frequency, with
+//      radix-R butterflies in registers and LDS exchanges between stages; the
+//      result stays in registers in digit-reversed slot order;
+//   3. for every template of its group: multiplies by the bank row (stored in
+//      the same slot order, so no reorder), runs the inverse FFT (decimation
+//      in time, natural-order output; the 1/L is folded into the bank), keeps
+//      outputs j in [m/2, m/2 + U) and writes |y|^2 straight to the power
+//      plane with non-temporal stores.
+// The paper runs the per-template inverse FFT on shared-memory-resident data
+// inside one thread block (Section 3); here each thread holds E = L / T
+// elements in VGPRs, the first inverse stage consumes the forward result
+// without touching LDS, and only the remaining P - 1 stages exchange
+// through a padded LDS buffer.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <type_traits>
+
+#include "fft_radix.hpp"
+#include "layout.hpp"
+#include "ols_variants.hpp"
+
+namespace fdas {
+
+template <int Begin, int End, class F>
+__device__ __forceinline__ void static_for_up(F &&f) {
+  if constexpr (Begin < End) {
+    f(std::integral_constant<int, Begin>{});
+    static_for_up<Begin + 1, End>(f);
+  }
+}
+template <int Begin, int End, class F>  // Begin, Begin-1, ..., End (inclusive)
+__device__ __forceinline__ void static_for_down(F &&f) {
+  if constexpr (Begin >= End) {
+    f(std::integral_constant<int, Begin>{});
+    static_for_down<Begin - 1, End>(f);
+  }
+}
+
+constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v >> 1); }
+
+template <int L_, int T_, int... Rs>
+struct Geo {
+  static constexpr int L = L_;
+  static constexpr int T = T_;
+  static constexpr int E = L_ / T_;
+  static constexpr int P = sizeof...(Rs);
+  static constexpr int R[P] = {Rs...};
+  static constexpr int S(int i) {
+    int s = 1;
+    for (int j = i + 1; j < P; ++j) s *= R[j];
+    return s;
+  }
+  static constexpr int B(int i) { return E / R[i]; }
+  static constexpr int PADSH = ilog2(R[P - 1]);
+  static constexpr int LP = L + (L >> PADSH);  // padded LDS length per segment
+  // offsets of each stage's inverse twiddles in a flat register array
+  static constexpr int TWOFF(int i) {
+    int o = 0;
+    for (int j = 0; j < i; ++j) o += B(j) * (R[j] - 1);
+    return o;
+  }
+  static constexpr int NTW = TWOFF(P - 1);
+};
+
+template <class Gm>
+__device__ __forceinline__ int pad(int a) {
+  return a + (a >> Gm::PADSH);
+}
+
+// Address of element n of the j-th butterfly of thread t in stage I.
+template <class Gm, int I>
+__device__ __forceinline__ int stage_addr(int t, int j, int n) {
+  constexpr int S = Gm::S(I), R = Gm::R[I];
+  const int b = t + j * Gm::T;
+  const int prefix = b / S, mi = b % S;
+  return prefix * R * S + n * S + mi;
+}
+template <class Gm, int I>
+__device__ __forceinline__ int stage_suffix(int t, int j) {
+  return (t + j * Gm::T) % Gm::S(I);
+}
+
+// Registers in the layout of stage A -> LDS -> registers in the layout of stage B.
+template <class Gm, int A, int Bst>
+__device__ __forceinline__ void exchange(c32 (&d)[Gm::E], c32 *buf, int t) {
+  constexpr int RA = Gm::R[A], RB = Gm::R[Bst];
+#pragma unroll
+  for (int j = 0; j < Gm::B(A); ++j)
+#pragma unroll
+    for (int n = 0; n < RA; ++n) buf[pad<Gm>(stage_addr<Gm, A>(t, j, n))] = d[j * RA + n];
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < Gm::B(Bst); ++j)
+#pragma unroll
+    for (int n = 0; n < RB; ++n) d[j * RB + n] = buf[pad<Gm>(stage_addr<Gm, Bst>(t, j, n))];
+}
+
+template <class Gm, int G, int NBUF>
+__global__ void __launch_bounds__(Gm::T *G)
+    ols_fp32_kernel(const c32 *__restrict__ spec, int64_t nbins, const c32 *__restrict__ bank,
+                    const c32 *__restrict__ tw, float *__restrict__ power, int64_t ld, int nseg,
+                    int U, int half, int nz, int zpb, int nsb) {
+  constexpr int L = Gm::L, T = Gm::T, E = Gm::E, P = Gm::P;
+  __shared__ c32 lds[NBUF][G][Gm::LP];
+
+  const int tid = threadIdx.x;
+  const int sg = tid / T;
+  const int t = tid % T;
+  const int sb = blockIdx.x % nsb;
+  const int zg = blockIdx.x / nsb;
+  const int s = sb * G + sg;
+  const int64_t seg0 = (int64_t)s * U - half;
+  const bool active = s < nseg;
+
+  c32 x[E];
+  // stage 0 input: element n of butterfly b = t + j T sits at n * S0 + b
+  {
+    constexpr int S0 = Gm::S(0), R0 = Gm::R[0];
+#pragma unroll
+    for (int j = 0; j < Gm::B(0); ++j)
+#pragma unroll
+      for (int n = 0; n < R0; ++n) {
+        const int64_t g = seg0 + n * S0 + t + j * T;
+        c32 v = {0.f, 0.f};
+        if (active && g >= 0 && g < nbins) v = spec[g];
+        x[j * R0 + n] = v;
+      }
+  }
+
+  int nb = 0;  // running LDS buffer index
+  // forward, decimation in frequency
+  static_for_up<0, P>([&](auto ic) {
+    constexpr int I = decltype(ic)::value;
+    constexpr int R = Gm::R[I];
+    if constexpr (I > 0) {
+      if constexpr (NBUF == 1) {
+        if (I > 1) __syncthreads();
+      }
+      exchange<Gm, I - 1, I>(x, lds[nb % NBUF][sg], t);
+      ++nb;
+    }
+#pragma unroll
+    for (int j = 0; j < Gm::B(I); ++j) {
+      dft<-1, R>(&x[j * R]);
+      if constexpr (I < P - 1) {
+        constexpr int N = R * Gm::S(I);
+        const int mi = stage_suffix<Gm, I>(t, j);
+#pragma unroll
+        for (int k = 1; k < R; ++k) x[j * R + k] = cmul(x[j * R + k], tw[(k * mi) * (L / N)]);
+      }
+    }
+  });
+
+  // inverse twiddles, reused by every template
+  c32 itw[Gm::NTW > 0 ? Gm::NTW : 1];
+  static_for_up<0, P - 1>([&](auto ic) {
+    constexpr int I = decltype(ic)::value;
+    constexpr int R = Gm::R[I];
+    constexpr int N = R * Gm::S(I);
+#pragma unroll
+    for (int j = 0; j < Gm::B(I); ++j) {
+      const int mi = stage_suffix<Gm, I>(t, j);
+#pragma unroll
+      for (int k = 1; k < R; ++k) itw[Gm::TWOFF(I) + j * (R - 1) + k - 1] = tw[(k * mi) * (L / N)];
+    }
+  });
+
+  const int z0 = zg * zpb;
+  const int z1 = min(nz, z0 + zpb);
+  for (int iz = z0; iz < z1; ++iz) {
+    c32 y[E];
+    const c32 *brow = bank + (int64_t)iz * L + t;
+#pragma unroll
+    for (int e = 0; e < E; ++e) y[e] = cmul(x[e], brow[e * T]);
+
+    // inverse, decimation in time: stages P-1 .. 0
+    static_for_down<P - 1, 0>([&](auto ic) {
+      constexpr int I = decltype(ic)::value;
+      constexpr int R = Gm::R[I];
+      if constexpr (I < P - 1) {
+        if constexpr (NBUF == 1) __syncthreads();
+        exchange<Gm, I + 1, I>(y, lds[nb % NBUF][sg], t);
+        ++nb;
+#pragma unroll
+        for (int j = 0; j < Gm::B(I); ++j)
+#pragma unroll
+          for (int k = 1; k < R; ++k)
+            y[j * R + k] = cmulc(y[j * R + k], itw[Gm::TWOFF(I) + j * (R - 1) + k - 1]);
+      }
+#pragma unroll
+      for (int j = 0; j < Gm::B(I); ++j) dft<+1, R>(&y[j * R]);
+    });
+
+    // outputs: slot j*R0 + n holds index n * S0 + t + j T of the segment
+    if (active) {
+      constexpr int S0 = Gm::S(0), R0 = Gm::R[0];
+      float *prow = power + (int64_t)iz * ld + (int64_t)s * U - half;
+#pragma unroll
+      for (int j = 0; j < Gm::B(0); ++j)
+#pragma unroll
+        for (int n = 0; n < R0; ++n) {
+          const int o = n * S0 + t + j * T;
+          const int64_t r = (int64_t)s * U + o - half;
+          if (o >= half && o < half + U && r < nbins) {
+            const c32 v = y[j * R0 + n];
+            __builtin_nontemporal_store(__builtin_fmaf(v.x, v.x, v.y * v.y), prow + o);
+          }
+        }
+    }
+  }
+}
+
+// ---- variant registry ------------------------------------------------------
+
+template <class Gm, int G, int NBUF>
+static hipError_t launch_variant(const OlsArgs &a, hipStream_t st) {
+  const int nsb = (a.nseg + G - 1) / G;
+  const int nzg = (a.nz + a.zpb - 1) / a.zpb;
+  const long blocks = (long)nsb * nzg;
+  hipLaunchKernelGGL((ols_fp32_kernel<Gm, G, NBUF>), dim3((unsigned)blocks), dim3(Gm::T * G), 0,
+                     st, static_cast<const c32 *>(a.spec), a.nbins,
+                     static_cast<const c32 *>(a.bank), static_cast<const c32 *>(a.tw), a.power,
+                     a.ld, a.nseg, a.U, a.half, a.nz, a.zpb, nsb);
+  return hipGetLastError();
+}
+
+template <class Gm, int G, int NBUF>
+static constexpr OlsVariant make_variant(const char *name) {
+  OlsVariant v{};
+  v.name = name;
+  v.L = Gm::L;
+  v.T = Gm::T;
+  v.G = G;
+  v.nbuf = NBUF;
+  v.lay.L = Gm::L;
+  v.lay.T = Gm::T;
+  v.lay.E = Gm::E;
+  v.lay.P = Gm::P;
+  for (int i = 0; i < kMaxStages; ++i) v.lay.R[i] = i < Gm::P ? Gm::R[i] : 1;
+  v.lds_bytes = NBUF * G * Gm::LP * 8;
+  v.launch = &launch_variant<Gm, G, NBUF>;
+  return v;
+}
+
+static const OlsVariant kFp32Variants[] = {
+    make_variant<Geo<256, 16, 16, 16>, 4, 1>("fp32_L256_t16x4_r16.16"),
+    make_variant<Geo<256, 32, 4, 8, 8>, 2, 1>("fp32_L256_t32x2_r4.8.8"),
+    make_variant<Geo<512, 32, 2, 16, 16>, 2, 1>("fp32_L512_t32x2_r2.16.16"),
+    make_variant<Geo<512, 64, 8, 8, 8>, 1, 1>("fp32_L512_t64_r8.8.8"),
+    make_variant<Geo<1024, 64, 4, 16, 16>, 1, 1>("fp32_L1024_t64_r4.16.16"),
+    make_variant<Geo<1024, 128, 2, 8, 8, 8>, 1, 1>("fp32_L1024_t128_r2.8.8.8"),
+    make_variant<Geo<2048, 128, 8, 16, 16>, 1, 1>("fp32_L2048_t128_r8.16.16"),
+    make_variant<Geo<2048, 128, 8, 16, 16>, 1, 2>("fp32_L2048_t128_r8.16.16_db"),
+    make_variant<Geo<2048, 256, 4, 8, 8, 8>, 1, 1>("fp32_L2048_t256_r4.8.8.8"),
+    make_variant<Geo<4096, 256, 16, 16, 16>, 1, 1>("fp32_L4096_t256_r16.16.16"),
+    make_variant<Geo<4096, 512, 8, 8, 8, 8>, 1, 1>("fp32_L4096_t512_r8.8.8.8"),
+    make_variant<Geo<8192, 512, 2, 16, 16, 16>, 1, 1>("fp32_L8192_t512_r2.16.16.16"),
+    make_variant<Geo<8192, 1024, 2, 8, 8, 8, 8>, 1, 1>("fp32_L8192_t1024_r2.8.8.8.8"),
+    make_variant<Geo<16384, 1024, 4, 16, 16, 16>, 1, 1>("fp32_L16384_t1024_r4.16.16.16"),
+};
+
+const OlsVariant *fp32_variants(int *count) {
+  *count = (int)(sizeof(kFp32Variants) / sizeof(kFp32Variants[0]));
+  return kFp32Variants;
+}
+
+}  // namespace fdas

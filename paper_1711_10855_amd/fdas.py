@@ -1,0 +1,249 @@
+"""Thin ctypes binding of the C ABI in include/fdas.h.
+
+Argument marshalling only: every step of the correlation runs in the HIP
+library ``libfdas.so`` built next to this file. PyTorch is used for device
+memory and streams; the functions take and return torch tensors and pass
+their device pointers and the current HIP stream through the ABI. If the
+library is missing, ``load()`` raises -- there is no fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfdas.so")
+
+OK = 0
+ERR_INVALID = -1
+ERR_UNSUPPORTED = -2
+ERR_NOMEM = -3
+ERR_DEVICE = -4
+
+FP32 = 0
+MIXED_FP16 = 1
+MIXED_BF16 = 2
+PRECISIONS = {"fp32": FP32, "fp16": MIXED_FP16, "bf16": MIXED_BF16}
+
+FLAG_SPLIT = 1
+FLAG_AUTOTUNE = 2
+
+EXPORTS = (
+    "fdas_plane_rows", "fdas_resolve_params", "fdas_make_templates", "fdas_plan",
+    "fdas_plan_get_info", "fdas_plan_bank", "fdas_convolve", "fdas_convolve_batch",
+    "fdas_destroy", "fdas_status_string", "fdas_last_error",
+)
+
+
+class Params(C.Structure):
+    _fields_ = [("zmax", C.c_double), ("dz", C.c_double), ("m", C.c_int),
+                ("seg_len", C.c_int), ("precision", C.c_int), ("flags", C.c_uint)]
+
+
+class Series(C.Structure):
+    _fields_ = [("spectrum", C.c_void_p), ("nbins", C.c_int64), ("zmax", C.c_double),
+                ("power", C.c_void_p), ("ld", C.c_int64)]
+
+
+class PlanInfo(C.Structure):
+    _fields_ = [("nz", C.c_int), ("m", C.c_int), ("seg_len", C.c_int), ("valid", C.c_int),
+                ("precision", C.c_int), ("flags", C.c_uint), ("threads", C.c_int),
+                ("templates_per_block", C.c_int), ("segments_per_block", C.c_int),
+                ("bank_bytes", C.c_size_t), ("plan_ms", C.c_double), ("kernel", C.c_char * 64)]
+
+
+class FdasError(RuntimeError):
+    def __init__(self, status: int, what: str, detail: str):
+        super().__init__(f"{what}: {status} ({detail})")
+        self.status = status
+
+
+_lib = None
+
+
+def load():
+    """Load libfdas.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing; run paper_1711_10855_amd.build first")
+    lib = C.CDLL(LIB_PATH)
+    P = C.POINTER
+    lib.fdas_plane_rows.argtypes = [P(Params)]
+    lib.fdas_plane_rows.restype = C.c_int
+    lib.fdas_resolve_params.argtypes = [P(Params), P(Params)]
+    lib.fdas_resolve_params.restype = C.c_int
+    lib.fdas_make_templates.argtypes = [P(Params), C.c_void_p, P(C.c_size_t), C.c_void_p]
+    lib.fdas_make_templates.restype = C.c_int
+    lib.fdas_plan.argtypes = [P(C.c_void_p), P(Params), C.c_int, C.c_void_p]
+    lib.fdas_plan.restype = C.c_int
+    lib.fdas_plan_get_info.argtypes = [C.c_void_p, P(PlanInfo)]
+    lib.fdas_plan_get_info.restype = C.c_int
+    lib.fdas_plan_bank.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
+    lib.fdas_plan_bank.restype = C.c_int
+    lib.fdas_convolve.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
+                                  C.c_void_p]
+    lib.fdas_convolve.restype = C.c_int
+    lib.fdas_convolve_batch.argtypes = [C.c_void_p, P(Series), C.c_int, C.c_void_p]
+    lib.fdas_convolve_batch.restype = C.c_int
+    lib.fdas_destroy.argtypes = [C.c_void_p]
+    lib.fdas_destroy.restype = C.c_int
+    lib.fdas_status_string.argtypes = [C.c_int]
+    lib.fdas_status_string.restype = C.c_char_p
+    lib.fdas_last_error.argtypes = []
+    lib.fdas_last_error.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+def last_error() -> str:
+    return load().fdas_last_error().decode()
+
+
+def _check(status: int, what: str):
+    if status != OK:
+        raise FdasError(status, what, last_error())
+
+
+def params(zmax, dz, m=0, seg_len=0, precision="fp32", flags=0) -> Params:
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    return Params(float(zmax), float(dz), int(m or 0), int(seg_len or 0), prec, int(flags))
+
+
+def plane_rows(zmax, dz) -> int:
+    n = load().fdas_plane_rows(C.byref(params(zmax, dz)))
+    if n < 0:
+        _check(n, "fdas_plane_rows")
+    return n
+
+
+def resolve(zmax, dz, m=0, seg_len=0, precision="fp32", flags=0) -> Params:
+    out = Params()
+    _check(load().fdas_resolve_params(C.byref(params(zmax, dz, m, seg_len, precision, flags)),
+                                      C.byref(out)), "fdas_resolve_params")
+    return out
+
+
+def _stream(device=None):
+    import torch
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def make_templates(zmax, dz, m=0):
+    """FP64 templates H_{z_i}(q), complex128 tensor [nz, m+1] on the current device."""
+    import torch
+    p = params(zmax, dz, m)
+    nbytes = C.c_size_t(0)
+    _check(load().fdas_make_templates(C.byref(p), None, C.byref(nbytes), None),
+           "fdas_make_templates(size)")
+    r = resolve(zmax, dz, m)
+    nz = plane_rows(zmax, dz)
+    out = torch.empty((nz, r.m + 1), dtype=torch.complex128, device="cuda")
+    _check(load().fdas_make_templates(C.byref(p), C.c_void_p(out.data_ptr()), C.byref(nbytes),
+                                      _stream()), "fdas_make_templates")
+    return out
+
+
+@dataclass
+class Info:
+    nz: int
+    m: int
+    seg_len: int
+    valid: int
+    precision: int
+    flags: int
+    threads: int
+    templates_per_block: int
+    segments_per_block: int
+    bank_bytes: int
+    plan_ms: float
+    kernel: str
+
+
+class Plan:
+    """Owns an fdas plan (template bank, twiddles) on one device."""
+
+    def __init__(self, zmax, dz, m=0, seg_len=0, precision="fp32", flags=0, device=None):
+        import torch
+        self._lib = load()
+        self.params = params(zmax, dz, m, seg_len, precision, flags)
+        dev = torch.cuda.current_device() if device is None else int(device)
+        self.device = dev
+        h = C.c_void_p()
+        _check(self._lib.fdas_plan(C.byref(h), C.byref(self.params), dev, _stream(dev)), "fdas_plan")
+        self._h = h
+        self.info = self.get_info()
+
+    def get_info(self) -> Info:
+        i = PlanInfo()
+        _check(self._lib.fdas_plan_get_info(self._h, C.byref(i)), "fdas_plan_get_info")
+        return Info(i.nz, i.m, i.seg_len, i.valid, i.precision, i.flags, i.threads,
+                    i.templates_per_block, i.segments_per_block, i.bank_bytes, i.plan_ms,
+                    i.kernel.decode())
+
+    @property
+    def nz(self) -> int:
+        return self.info.nz
+
+    def bank(self):
+        """The Fourier-domain bank, natural order, complex64 [nz, L] (testing)."""
+        import torch
+        out = torch.empty((self.info.nz, self.info.seg_len), dtype=torch.complex64,
+                          device=f"cuda:{self.device}")
+        _check(self._lib.fdas_plan_bank(self._h, C.c_void_p(out.data_ptr()),
+                                        out.numel() * 8, _stream(self.device)), "fdas_plan_bank")
+        return out
+
+    def convolve(self, spectrum, out=None, ld=None):
+        """power[nz, nbins] (float32) for a complex64 device spectrum."""
+        import torch
+        if spectrum.dtype != torch.complex64 or not spectrum.is_cuda or spectrum.dim() != 1:
+            raise TypeError("spectrum must be a 1-D complex64 CUDA tensor")
+        spectrum = spectrum.contiguous()
+        nbins = spectrum.numel()
+        if out is None:
+            ld = nbins if ld is None else int(ld)
+            out = torch.empty((self.info.nz, ld), dtype=torch.float32, device=spectrum.device)
+        else:
+            ld = out.stride(0) if ld is None else int(ld)
+        _check(self._lib.fdas_convolve(self._h, C.c_void_p(spectrum.data_ptr()), nbins,
+                                       C.c_void_p(out.data_ptr()), ld, _stream(spectrum.device)),
+               "fdas_convolve")
+        return out[:, :nbins] if out.shape[1] != nbins else out
+
+    def convolve_batch(self, spectra, zmaxs, outs):
+        """Batched form: one launch over every series (see fdas_convolve_batch)."""
+        n = len(spectra)
+        arr = (Series * n)()
+        for i, (s, z, o) in enumerate(zip(spectra, zmaxs, outs)):
+            arr[i] = Series(C.c_void_p(s.data_ptr()), s.numel(), float(z),
+                            C.c_void_p(o.data_ptr()), o.stride(0))
+        dev = spectra[0].device
+        _check(self._lib.fdas_convolve_batch(self._h, arr, n, _stream(dev)), "fdas_convolve_batch")
+        return outs
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(self._lib.fdas_destroy(self._h), "fdas_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def convolve(spectrum, zmax, dz, m=0, seg_len=0, precision="fp32", flags=0):
+    """One-shot: plan, correlate, destroy. Returns power [nz, nbins] float32."""
+    with Plan(zmax, dz, m, seg_len, precision, flags, device=spectrum.device.index) as p:
+        return p.convolve(spectrum)

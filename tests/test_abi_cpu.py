@@ -1,0 +1,107 @@
+"""The C-ABI library loads, exports every declared symbol, and rejects bad
+arguments on the host before any device work (CPU only; no compute calls)."""
+
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1711_10855_amd import fdas
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fdas.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fdas_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return fdas.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    syms = declared_symbols()
+    assert len(syms) >= 11
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert set(fdas.EXPORTS) <= set(syms)
+
+
+def test_status_strings(lib):
+    assert lib.fdas_status_string(0) == b"ok"
+    assert lib.fdas_status_string(-1) == b"invalid argument"
+    assert lib.fdas_status_string(-2) == b"unsupported configuration"
+    assert lib.fdas_status_string(12345) == b"unknown status"
+
+
+@pytest.mark.parametrize("zmax,dz,nz", [(16, 2, 17), (100, 2, 101), (200, 2, 201), (0, 2, 1),
+                                        (3, 2, 4), (1.5, 0.5, 7)])
+def test_plane_rows(zmax, dz, nz):
+    assert fdas.plane_rows(zmax, dz) == nz
+
+
+@pytest.mark.parametrize("zmax,dz", [(-1, 2), (3, 4), (10, 0), (10, -2), (float("nan"), 2),
+                                     (float("inf"), 2), (1e9, 1e-3)])
+def test_plane_rows_invalid(zmax, dz):
+    with pytest.raises(fdas.FdasError) as e:
+        fdas.plane_rows(zmax, dz)
+    assert e.value.status == fdas.ERR_INVALID
+
+
+def test_resolve_defaults():
+    r = fdas.resolve(16, 2)
+    assert r.m == 64 and r.seg_len >= 256 and r.seg_len > r.m
+    r = fdas.resolve(100, 2)
+    assert r.m == 256
+    r = fdas.resolve(200, 2)
+    assert r.m == 512
+    r = fdas.resolve(100, 2, 256, 2048)
+    assert (r.m, r.seg_len) == (256, 2048)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(m=7), fdas.ERR_INVALID),                  # odd m
+    (dict(m=-4), fdas.ERR_INVALID),
+    (dict(m=256, seg_len=256), fdas.ERR_INVALID),   # L <= m
+    (dict(m=64, seg_len=300), fdas.ERR_UNSUPPORTED),  # not a power of two
+    (dict(m=64, seg_len=128), fdas.ERR_UNSUPPORTED),  # below the compiled set
+    (dict(m=64, seg_len=32768), fdas.ERR_UNSUPPORTED),
+    (dict(precision=7), fdas.ERR_INVALID),
+    (dict(flags=0x80), fdas.ERR_INVALID),
+])
+def test_resolve_rejects(kw, status):
+    with pytest.raises(fdas.FdasError) as e:
+        fdas.resolve(16, 2, **kw)
+    assert e.value.status == status
+    assert fdas.last_error() != ""
+
+
+def test_template_size_query_needs_no_device(lib):
+    p = fdas.params(16, 2, 64)
+    n = C.c_size_t(0)
+    assert lib.fdas_make_templates(C.byref(p), None, C.byref(n), None) == 0
+    assert n.value == 17 * 65 * 16
+    assert lib.fdas_make_templates(C.byref(p), None, None, None) == fdas.ERR_INVALID
+    small = C.c_size_t(10)
+    # a too-small buffer is rejected before any launch (the pointer is never used)
+    assert lib.fdas_make_templates(C.byref(p), C.c_void_p(0x1000), C.byref(small), None) == fdas.ERR_INVALID
+    assert small.value == 17 * 65 * 16
+
+
+def test_null_and_bad_arguments(lib):
+    assert lib.fdas_destroy(None) == 0
+    assert lib.fdas_plan(None, None, 0, None) == fdas.ERR_INVALID
+    h = C.c_void_p()
+    bad = fdas.params(3, 4)
+    assert lib.fdas_plan(C.byref(h), C.byref(bad), 0, None) == fdas.ERR_INVALID
+    assert h.value is None
+    assert lib.fdas_plan(C.byref(h), C.byref(fdas.params(16, 2)), -1, None) == fdas.ERR_INVALID
+    assert lib.fdas_convolve(None, C.c_void_p(8), 10, C.c_void_p(8), 10, None) == fdas.ERR_INVALID
+    assert lib.fdas_convolve_batch(None, None, 0, None) == fdas.ERR_INVALID
+    assert lib.fdas_plan_get_info(None, None) == fdas.ERR_INVALID
+    assert lib.fdas_plan_bank(None, None, 0, None) == fdas.ERR_INVALID
