@@ -41,20 +41,26 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-bins", type=int, default=1 << 20)
     ap.add_argument("--seg-len", type=int, default=None)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (for "
+                         "scaling HBM byte counters) and exit")
     return ap.parse_args()
 
 
 def traffic_from_profiles(kernel: str, workload: str):
     """HBM bytes per launch from the committed counter summary, if it was
-    taken on this exact kernel variant and workload (else None)."""
+    taken on this exact kernel variant, workload and kernel source (else None)."""
+    from paper_1711_10855_amd.profile_summary import source_hash
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
             rows = json.load(f)
     except (OSError, ValueError):
         return None
+    h = source_hash()
     for row in rows:
-        if row.get("kernel") == kernel and row.get("workload") == workload and row.get("current", True):
+        if (row.get("kernel") == kernel and row.get("workload") == workload
+                and row.get("source_hash") == h):
             return row.get("bytes_per_launch")
     return None
 
@@ -89,6 +95,16 @@ def main():
     import torch
 
     from paper_1711_10855_amd import fdas, synth
+
+    if args.calibrate_copy:
+        n = args.calibrate_copy << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": n, "launches": 3}))
+        return
 
     w = synth.WORKLOADS[args.workload]
     if w.nseries != 1 or w.precision != "fp32":

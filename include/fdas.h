@@ -166,6 +166,14 @@ int fdas_convolve_batch(fdas_plan_t plan, const fdas_series *series,
  * Synchronises the device the plan lives on.                                */
 int fdas_destroy(fdas_plan_t plan);
 
+/* Names of the compiled hot-kernel variants for a segment length (0 = all)
+ * and precision (-1 = all), newline-separated, into the host buffer `buf` of
+ * `len` bytes (truncated, always NUL-terminated when len > 0; buf may be NULL
+ * with len 0 to count). Returns the number of variants or a negative status.
+ * A variant is forced for new plans by the FDAS_VARIANT environment
+ * variable; FDAS_ZPB overrides templates per work unit.                     */
+int fdas_kernel_variants(int seg_len, int precision, char *buf, size_t len);
+
 /* Static description of a status code.                                      */
 const char *fdas_status_string(int status);
 

@@ -123,6 +123,13 @@ const char *fdas_status_string(int status) {
 
 const char *fdas_last_error(void) { return g_last_error.c_str(); }
 
+int fdas_kernel_variants(int seg_len, int precision, char *buf, size_t len) {
+  if (seg_len < 0 || precision < -1 || precision > FDAS_MIXED_BF16)
+    return set_error(FDAS_ERR_INVALID, "bad seg_len %d or precision %d", seg_len, precision);
+  if (!buf && len) return set_error(FDAS_ERR_INVALID, "null buffer with nonzero length");
+  return list_variants(seg_len, precision, buf, len);
+}
+
 int fdas_plane_rows(const fdas_params *p) {
   if (!p) return set_error(FDAS_ERR_INVALID, "null params pointer");
   return validate_grid(p->zmax, p->dz);

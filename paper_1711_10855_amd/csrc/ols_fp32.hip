@@ -66,6 +66,29 @@ struct Geo {
     return o;
   }
   static constexpr int NTW = TWOFF(P - 1);
+  // Thread that owns address a in stage i (butterfly b = t + j T).
+  static constexpr int owner(int i, int a) {
+    const int s = S(i), r = R[i];
+    const int prefix = a / (r * s), mi = a % s;
+    return (prefix * s + mi) % T;
+  }
+  // An exchange between stages i and i+1 is wave-local when every address is
+  // owned by threads of the same 64-lane wave in both layouts; it then needs
+  // no workgroup barrier, only ordering within the wave.
+  static constexpr bool local(int i, int waves_per_seg_slot_base = 0) {
+    (void)waves_per_seg_slot_base;
+    if (T <= 64) return true;  // a segment never straddles a wave
+    for (int a = 0; a < L; ++a)
+      if (owner(i, a) / 64 != owner(i + 1, a) / 64) return false;
+    return true;
+  }
+  static constexpr bool any_block() {
+    for (int i = 0; i + 1 < P; ++i)
+      if (!local(i)) return true;
+    return false;
+  }
+  // two buffers when a block-wide exchange exists and they fit in LDS
+  static constexpr int NBUF = (any_block() && 2 * LP * 8 <= 80 * 1024) ? 2 : 1;
 };
 
 template <class Gm>
@@ -86,28 +109,53 @@ __device__ __forceinline__ int stage_suffix(int t, int j) {
   return (t + j * Gm::T) % Gm::S(I);
 }
 
-// Registers in the layout of stage A -> LDS -> registers in the layout of stage B.
+// Ordering of LDS traffic inside one wave (no workgroup barrier).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Registers in the layout of stage A -> LDS -> registers in the layout of
+// stage Bst. Block-wide exchanges flip the buffer so that one barrier per
+// exchange suffices; wave-local exchanges touch only addresses their own
+// wave owns and use the buffer of the next block-wide exchange.
 template <class Gm, int A, int Bst>
-__device__ __forceinline__ void exchange(c32 (&d)[Gm::E], c32 *buf, int t) {
+__device__ __forceinline__ void exchange(c32 (&d)[Gm::E], c32 *buf0, c32 *buf1, int &cur, int t) {
   constexpr int RA = Gm::R[A], RB = Gm::R[Bst];
+  constexpr int lo = A < Bst ? A : Bst;
+  constexpr bool loc = Gm::local(lo);
+  c32 *buf = cur ? buf1 : buf0;
 #pragma unroll
   for (int j = 0; j < Gm::B(A); ++j)
 #pragma unroll
     for (int n = 0; n < RA; ++n) buf[pad<Gm>(stage_addr<Gm, A>(t, j, n))] = d[j * RA + n];
-  __syncthreads();
+  if constexpr (loc) {
+    wave_sync();
+  } else {
+    __syncthreads();
+  }
 #pragma unroll
   for (int j = 0; j < Gm::B(Bst); ++j)
 #pragma unroll
     for (int n = 0; n < RB; ++n) d[j * RB + n] = buf[pad<Gm>(stage_addr<Gm, Bst>(t, j, n))];
+  if constexpr (loc) {
+    wave_sync();
+  } else if constexpr (Gm::NBUF == 2) {
+    cur ^= 1;
+  } else {
+    __syncthreads();  // single buffer: every read done before the next write
+  }
 }
 
-template <class Gm, int G, int NBUF>
-__global__ void __launch_bounds__(Gm::T *G)
+template <class Gm, int G, bool TWREG, bool PF, int WPE>
+__global__ void __launch_bounds__(Gm::T *G) __attribute__((amdgpu_waves_per_eu(WPE)))
     ols_fp32_kernel(const c32 *__restrict__ spec, int64_t nbins, const c32 *__restrict__ bank,
                     const c32 *__restrict__ tw, float *__restrict__ power, int64_t ld, int nseg,
                     int U, int half, int nz, int zpb, int nsb) {
   constexpr int L = Gm::L, T = Gm::T, E = Gm::E, P = Gm::P;
-  __shared__ c32 lds[NBUF][G][Gm::LP];
+  constexpr int NB = Gm::NBUF;
+  __shared__ c32 lds[NB][G][Gm::LP];
 
   const int tid = threadIdx.x;
   const int sg = tid / T;
@@ -117,6 +165,12 @@ __global__ void __launch_bounds__(Gm::T *G)
   const int s = sb * G + sg;
   const int64_t seg0 = (int64_t)s * U - half;
   const bool active = s < nseg;
+  c32 *buf0 = lds[0][sg];
+  c32 *buf1 = lds[NB - 1][sg];
+  int cur = 0;
+
+  const int z0 = zg * zpb;
+  const int z1 = min(nz, z0 + zpb);
 
   c32 x[E];
   // stage 0 input: element n of butterfly b = t + j T sits at n * S0 + b
@@ -132,19 +186,18 @@ __global__ void __launch_bounds__(Gm::T *G)
         x[j * R0 + n] = v;
       }
   }
+  c32 bnext[PF ? E : 1];
+  if constexpr (PF) {
+    const c32 *brow = bank + (int64_t)z0 * L + t;
+#pragma unroll
+    for (int e = 0; e < E; ++e) bnext[e] = brow[e * T];
+  }
 
-  int nb = 0;  // running LDS buffer index
   // forward, decimation in frequency
   static_for_up<0, P>([&](auto ic) {
     constexpr int I = decltype(ic)::value;
     constexpr int R = Gm::R[I];
-    if constexpr (I > 0) {
-      if constexpr (NBUF == 1) {
-        if (I > 1) __syncthreads();
-      }
-      exchange<Gm, I - 1, I>(x, lds[nb % NBUF][sg], t);
-      ++nb;
-    }
+    if constexpr (I > 0) exchange<Gm, I - 1, I>(x, buf0, buf1, cur, t);
 #pragma unroll
     for (int j = 0; j < Gm::B(I); ++j) {
       dft<-1, R>(&x[j * R]);
@@ -158,40 +211,54 @@ __global__ void __launch_bounds__(Gm::T *G)
   });
 
   // inverse twiddles, reused by every template
-  c32 itw[Gm::NTW > 0 ? Gm::NTW : 1];
-  static_for_up<0, P - 1>([&](auto ic) {
-    constexpr int I = decltype(ic)::value;
-    constexpr int R = Gm::R[I];
-    constexpr int N = R * Gm::S(I);
+  c32 itw[TWREG && Gm::NTW > 0 ? Gm::NTW : 1];
+  if constexpr (TWREG) {
+    static_for_up<0, P - 1>([&](auto ic) {
+      constexpr int I = decltype(ic)::value;
+      constexpr int R = Gm::R[I];
+      constexpr int N = R * Gm::S(I);
 #pragma unroll
-    for (int j = 0; j < Gm::B(I); ++j) {
-      const int mi = stage_suffix<Gm, I>(t, j);
+      for (int j = 0; j < Gm::B(I); ++j) {
+        const int mi = stage_suffix<Gm, I>(t, j);
 #pragma unroll
-      for (int k = 1; k < R; ++k) itw[Gm::TWOFF(I) + j * (R - 1) + k - 1] = tw[(k * mi) * (L / N)];
-    }
-  });
+        for (int k = 1; k < R; ++k)
+          itw[Gm::TWOFF(I) + j * (R - 1) + k - 1] = tw[(k * mi) * (L / N)];
+      }
+    });
+  }
 
-  const int z0 = zg * zpb;
-  const int z1 = min(nz, z0 + zpb);
   for (int iz = z0; iz < z1; ++iz) {
     c32 y[E];
-    const c32 *brow = bank + (int64_t)iz * L + t;
+    if constexpr (PF) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) y[e] = cmul(x[e], brow[e * T]);
+      for (int e = 0; e < E; ++e) y[e] = cmul(x[e], bnext[e]);
+      if (iz + 1 < z1) {
+        const c32 *brow = bank + (int64_t)(iz + 1) * L + t;
+#pragma unroll
+        for (int e = 0; e < E; ++e) bnext[e] = brow[e * T];
+      }
+    } else {
+      const c32 *brow = bank + (int64_t)iz * L + t;
+#pragma unroll
+      for (int e = 0; e < E; ++e) y[e] = cmul(x[e], brow[e * T]);
+    }
 
     // inverse, decimation in time: stages P-1 .. 0
     static_for_down<P - 1, 0>([&](auto ic) {
       constexpr int I = decltype(ic)::value;
       constexpr int R = Gm::R[I];
       if constexpr (I < P - 1) {
-        if constexpr (NBUF == 1) __syncthreads();
-        exchange<Gm, I + 1, I>(y, lds[nb % NBUF][sg], t);
-        ++nb;
+        exchange<Gm, I + 1, I>(y, buf0, buf1, cur, t);
+        constexpr int N = R * Gm::S(I);
 #pragma unroll
-        for (int j = 0; j < Gm::B(I); ++j)
+        for (int j = 0; j < Gm::B(I); ++j) {
+          const int mi = stage_suffix<Gm, I>(t, j);
 #pragma unroll
-          for (int k = 1; k < R; ++k)
-            y[j * R + k] = cmulc(y[j * R + k], itw[Gm::TWOFF(I) + j * (R - 1) + k - 1]);
+          for (int k = 1; k < R; ++k) {
+            const c32 w = TWREG ? itw[Gm::TWOFF(I) + j * (R - 1) + k - 1] : tw[(k * mi) * (L / N)];
+            y[j * R + k] = cmulc(y[j * R + k], w);
+          }
+        }
       }
 #pragma unroll
       for (int j = 0; j < Gm::B(I); ++j) dft<+1, R>(&y[j * R]);
@@ -200,7 +267,7 @@ __global__ void __launch_bounds__(Gm::T *G)
     // outputs: slot j*R0 + n holds index n * S0 + t + j T of the segment
     if (active) {
       constexpr int S0 = Gm::S(0), R0 = Gm::R[0];
-      float *prow = power + (int64_t)iz * ld + (int64_t)s * U - half;
+      float *prow = power + (int64_t)iz * ld;
 #pragma unroll
       for (int j = 0; j < Gm::B(0); ++j)
 #pragma unroll
@@ -209,7 +276,7 @@ __global__ void __launch_bounds__(Gm::T *G)
           const int64_t r = (int64_t)s * U + o - half;
           if (o >= half && o < half + U && r < nbins) {
             const c32 v = y[j * R0 + n];
-            __builtin_nontemporal_store(__builtin_fmaf(v.x, v.x, v.y * v.y), prow + o);
+            __builtin_nontemporal_store(__builtin_fmaf(v.x, v.x, v.y * v.y), prow + r);
           }
         }
     }
@@ -218,51 +285,55 @@ __global__ void __launch_bounds__(Gm::T *G)
 
 // ---- variant registry ------------------------------------------------------
 
-template <class Gm, int G, int NBUF>
+template <class Gm, int G, bool TWREG, bool PF, int WPE>
 static hipError_t launch_variant(const OlsArgs &a, hipStream_t st) {
   const int nsb = (a.nseg + G - 1) / G;
   const int nzg = (a.nz + a.zpb - 1) / a.zpb;
   const long blocks = (long)nsb * nzg;
-  hipLaunchKernelGGL((ols_fp32_kernel<Gm, G, NBUF>), dim3((unsigned)blocks), dim3(Gm::T * G), 0,
-                     st, static_cast<const c32 *>(a.spec), a.nbins,
+  hipLaunchKernelGGL((ols_fp32_kernel<Gm, G, TWREG, PF, WPE>), dim3((unsigned)blocks),
+                     dim3(Gm::T * G), 0, st, static_cast<const c32 *>(a.spec), a.nbins,
                      static_cast<const c32 *>(a.bank), static_cast<const c32 *>(a.tw), a.power,
                      a.ld, a.nseg, a.U, a.half, a.nz, a.zpb, nsb);
   return hipGetLastError();
 }
 
-template <class Gm, int G, int NBUF>
+template <class Gm, int G, bool TWREG, bool PF, int WPE = 1>
 static constexpr OlsVariant make_variant(const char *name) {
   OlsVariant v{};
   v.name = name;
   v.L = Gm::L;
   v.T = Gm::T;
   v.G = G;
-  v.nbuf = NBUF;
+  v.nbuf = Gm::NBUF;
   v.lay.L = Gm::L;
   v.lay.T = Gm::T;
   v.lay.E = Gm::E;
   v.lay.P = Gm::P;
   for (int i = 0; i < kMaxStages; ++i) v.lay.R[i] = i < Gm::P ? Gm::R[i] : 1;
-  v.lds_bytes = NBUF * G * Gm::LP * 8;
-  v.launch = &launch_variant<Gm, G, NBUF>;
+  v.lds_bytes = Gm::NBUF * G * Gm::LP * 8;
+  v.launch = &launch_variant<Gm, G, TWREG, PF, WPE>;
   return v;
 }
 
+// Name: fp32_L<len>_t<threads per segment>[x<segments per block>]_r<radices>
+//       [_tg: twiddles re-read from the table | _np: no bank prefetch]
 static const OlsVariant kFp32Variants[] = {
-    make_variant<Geo<256, 16, 16, 16>, 4, 1>("fp32_L256_t16x4_r16.16"),
-    make_variant<Geo<256, 32, 4, 8, 8>, 2, 1>("fp32_L256_t32x2_r4.8.8"),
-    make_variant<Geo<512, 32, 2, 16, 16>, 2, 1>("fp32_L512_t32x2_r2.16.16"),
-    make_variant<Geo<512, 64, 8, 8, 8>, 1, 1>("fp32_L512_t64_r8.8.8"),
-    make_variant<Geo<1024, 64, 4, 16, 16>, 1, 1>("fp32_L1024_t64_r4.16.16"),
-    make_variant<Geo<1024, 128, 2, 8, 8, 8>, 1, 1>("fp32_L1024_t128_r2.8.8.8"),
-    make_variant<Geo<2048, 128, 8, 16, 16>, 1, 1>("fp32_L2048_t128_r8.16.16"),
-    make_variant<Geo<2048, 128, 8, 16, 16>, 1, 2>("fp32_L2048_t128_r8.16.16_db"),
-    make_variant<Geo<2048, 256, 4, 8, 8, 8>, 1, 1>("fp32_L2048_t256_r4.8.8.8"),
-    make_variant<Geo<4096, 256, 16, 16, 16>, 1, 1>("fp32_L4096_t256_r16.16.16"),
-    make_variant<Geo<4096, 512, 8, 8, 8, 8>, 1, 1>("fp32_L4096_t512_r8.8.8.8"),
-    make_variant<Geo<8192, 512, 2, 16, 16, 16>, 1, 1>("fp32_L8192_t512_r2.16.16.16"),
-    make_variant<Geo<8192, 1024, 2, 8, 8, 8, 8>, 1, 1>("fp32_L8192_t1024_r2.8.8.8.8"),
-    make_variant<Geo<16384, 1024, 4, 16, 16, 16>, 1, 1>("fp32_L16384_t1024_r4.16.16.16"),
+    // the first entry for each length is the default for that length
+    make_variant<Geo<256, 32, 4, 8, 8>, 2, true, true, 4>("fp32_L256_t32x2_r4.8.8"),
+    make_variant<Geo<256, 16, 16, 16>, 4, true, true>("fp32_L256_t16x4_r16.16"),
+    make_variant<Geo<512, 64, 8, 8, 8>, 1, true, true, 4>("fp32_L512_t64_r8.8.8"),
+    make_variant<Geo<512, 32, 2, 16, 16>, 2, false, true>("fp32_L512_t32x2_r2.16.16_tg"),
+    make_variant<Geo<1024, 64, 4, 16, 16>, 1, false, true>("fp32_L1024_t64_r4.16.16_tg"),
+    make_variant<Geo<1024, 128, 2, 8, 8, 8>, 1, true, true, 4>("fp32_L1024_t128_r2.8.8.8"),
+    make_variant<Geo<2048, 128, 8, 16, 16>, 1, false, true>("fp32_L2048_t128_r8.16.16_tg"),
+    make_variant<Geo<2048, 128, 8, 16, 16>, 1, true, false>("fp32_L2048_t128_r8.16.16_np"),
+    make_variant<Geo<2048, 256, 4, 8, 8, 8>, 1, true, true, 3>("fp32_L2048_t256_r4.8.8.8"),
+    make_variant<Geo<2048, 256, 4, 8, 8, 8>, 1, false, true, 3>("fp32_L2048_t256_r4.8.8.8_tg"),
+    make_variant<Geo<4096, 256, 16, 16, 16>, 1, false, true>("fp32_L4096_t256_r16.16.16_tg"),
+    make_variant<Geo<4096, 512, 8, 8, 8, 8>, 1, false, true>("fp32_L4096_t512_r8.8.8.8_tg"),
+    make_variant<Geo<8192, 512, 2, 16, 16, 16>, 1, false, true>("fp32_L8192_t512_r2.16.16.16_tg"),
+    make_variant<Geo<8192, 1024, 2, 8, 8, 8, 8>, 1, false, true>("fp32_L8192_t1024_r2.8.8.8.8_tg"),
+    make_variant<Geo<16384, 1024, 4, 16, 16, 16>, 1, false, false>("fp32_L16384_t1024_r4.16.16.16_tg"),
 };
 
 const OlsVariant *fp32_variants(int *count) {

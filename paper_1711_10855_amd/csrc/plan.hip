@@ -112,6 +112,25 @@ void plan_info(fdas_plan_t pl, fdas_plan_info *info) {
   std::strncpy(info->kernel, pl->var->name, sizeof(info->kernel) - 1);
 }
 
+int list_variants(int seg_len, int precision, char *buf, size_t len) {
+  int n = 0, count = 0;
+  const OlsVariant *v = fp32_variants(&n);
+  std::string out;
+  if (precision == -1 || precision == FDAS_FP32) {
+    for (int i = 0; i < n; ++i) {
+      if (seg_len && v[i].L != seg_len) continue;
+      out += v[i].name;
+      out += '\n';
+      ++count;
+    }
+  }
+  if (buf && len > 0) {
+    std::strncpy(buf, out.c_str(), len - 1);
+    buf[len - 1] = '\0';
+  }
+  return count;
+}
+
 int plan_rows(fdas_plan_t pl) { return pl->nz; }
 int plan_seg_len(fdas_plan_t pl) { return pl->L; }
 int plan_device(fdas_plan_t pl) { return pl->device; }

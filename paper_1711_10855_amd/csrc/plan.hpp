@@ -16,6 +16,7 @@ bool mixed_supported(int seg_len);
 
 int build_plan(fdas_plan_t *out, const fdas_params &p, int nz, int device, hipStream_t s);
 void plan_info(fdas_plan_t plan, fdas_plan_info *info);
+int list_variants(int seg_len, int precision, char *buf, size_t len);
 int plan_rows(fdas_plan_t plan);
 int plan_seg_len(fdas_plan_t plan);
 int plan_device(fdas_plan_t plan);

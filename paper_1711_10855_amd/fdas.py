@@ -33,7 +33,7 @@ FLAG_AUTOTUNE = 2
 EXPORTS = (
     "fdas_plane_rows", "fdas_resolve_params", "fdas_make_templates", "fdas_plan",
     "fdas_plan_get_info", "fdas_plan_bank", "fdas_convolve", "fdas_convolve_batch",
-    "fdas_destroy", "fdas_status_string", "fdas_last_error",
+    "fdas_destroy", "fdas_status_string", "fdas_last_error", "fdas_kernel_variants",
 )
 
 
@@ -70,6 +70,10 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing; run paper_1711_10855_amd.build first")
+    # torch ships its own HIP runtime under the same soname; it must be the one
+    # in the process before libfdas.so resolves its HIP dependency, so that the
+    # library and torch's allocator and streams share one runtime instance.
+    import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
     P = C.POINTER
     lib.fdas_plane_rows.argtypes = [P(Params)]
@@ -93,6 +97,8 @@ def load():
     lib.fdas_destroy.restype = C.c_int
     lib.fdas_status_string.argtypes = [C.c_int]
     lib.fdas_status_string.restype = C.c_char_p
+    lib.fdas_kernel_variants.argtypes = [C.c_int, C.c_int, C.c_char_p, C.c_size_t]
+    lib.fdas_kernel_variants.restype = C.c_int
     lib.fdas_last_error.argtypes = []
     lib.fdas_last_error.restype = C.c_char_p
     _lib = lib
@@ -125,6 +131,17 @@ def resolve(zmax, dz, m=0, seg_len=0, precision="fp32", flags=0) -> Params:
     _check(load().fdas_resolve_params(C.byref(params(zmax, dz, m, seg_len, precision, flags)),
                                       C.byref(out)), "fdas_resolve_params")
     return out
+
+
+def kernel_variants(seg_len=0, precision=-1):
+    """Names of the compiled hot-kernel variants (host-only query)."""
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    n = load().fdas_kernel_variants(int(seg_len), prec, None, 0)
+    if n < 0:
+        _check(n, "fdas_kernel_variants")
+    buf = C.create_string_buffer(64 * (n + 1))
+    load().fdas_kernel_variants(int(seg_len), prec, buf, len(buf))
+    return [x for x in buf.value.decode().split("\n") if x]
 
 
 def _stream(device=None):

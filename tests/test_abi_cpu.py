@@ -105,3 +105,12 @@ def test_null_and_bad_arguments(lib):
     assert lib.fdas_convolve_batch(None, None, 0, None) == fdas.ERR_INVALID
     assert lib.fdas_plan_get_info(None, None) == fdas.ERR_INVALID
     assert lib.fdas_plan_bank(None, None, 0, None) == fdas.ERR_INVALID
+
+
+def test_kernel_variant_listing():
+    names = fdas.kernel_variants()
+    assert len(names) >= 8
+    for L in (256, 512, 1024, 2048, 4096, 8192, 16384):
+        sub = fdas.kernel_variants(L, "fp32")
+        assert sub and all(f"_L{L}_" in n for n in sub)
+    assert fdas.load().fdas_kernel_variants(-1, 0, None, 0) == fdas.ERR_INVALID

@@ -68,22 +68,12 @@ def test_workload1_full_plane(gpu):
 
 
 def _variants():
-    from paper_1711_10855_amd import fdas  # noqa: F401
-    names = []
-    for L, vs in VARIANTS.items():
-        names += [(L, v) for v in vs]
-    return names
-
-
-VARIANTS = {
-    256: ["fp32_L256_t16x4_r16.16", "fp32_L256_t32x2_r4.8.8"],
-    512: ["fp32_L512_t32x2_r2.16.16", "fp32_L512_t64_r8.8.8"],
-    1024: ["fp32_L1024_t64_r4.16.16", "fp32_L1024_t128_r2.8.8.8"],
-    2048: ["fp32_L2048_t128_r8.16.16", "fp32_L2048_t128_r8.16.16_db", "fp32_L2048_t256_r4.8.8.8"],
-    4096: ["fp32_L4096_t256_r16.16.16", "fp32_L4096_t512_r8.8.8.8"],
-    8192: ["fp32_L8192_t512_r2.16.16.16", "fp32_L8192_t1024_r2.8.8.8.8"],
-    16384: ["fp32_L16384_t1024_r4.16.16.16"],
-}
+    from paper_1711_10855_amd import fdas
+    out = []
+    for name in fdas.kernel_variants(0, "fp32"):
+        L = int(name.split("_L")[1].split("_")[0])
+        out.append((L, name))
+    return out
 
 
 @pytest.mark.parametrize("L,name", _variants())
