@@ -148,29 +148,16 @@ __device__ __forceinline__ void exchange(c32 (&d)[Gm::E], c32 *buf0, c32 *buf1, 
   }
 }
 
-template <class Gm, int G, bool TWREG, bool PF, int WPE>
-__global__ void __launch_bounds__(Gm::T *G) __attribute__((amdgpu_waves_per_eu(WPE)))
-    ols_fp32_kernel(const c32 *__restrict__ spec, int64_t nbins, const c32 *__restrict__ bank,
-                    const c32 *__restrict__ tw, float *__restrict__ power, int64_t ld, int nseg,
-                    int U, int half, int nz, int zpb, int nsb) {
+// One work unit: segment s of a spectrum, bank rows [z0, z1), plane rows
+// (iz - row_base). `cur` carries the LDS buffer parity across units.
+template <class Gm, bool TWREG, bool PF>
+__device__ __forceinline__ void ols_unit(const c32 *__restrict__ spec, int64_t nbins,
+                                         const c32 *__restrict__ bank, const c32 *__restrict__ tw,
+                                         float *__restrict__ power, int64_t ld, int s, bool active,
+                                         int U, int half, int z0, int z1, int row_base, c32 *buf0,
+                                         c32 *buf1, int &cur, int t) {
   constexpr int L = Gm::L, T = Gm::T, E = Gm::E, P = Gm::P;
-  constexpr int NB = Gm::NBUF;
-  __shared__ c32 lds[NB][G][Gm::LP];
-
-  const int tid = threadIdx.x;
-  const int sg = tid / T;
-  const int t = tid % T;
-  const int sb = blockIdx.x % nsb;
-  const int zg = blockIdx.x / nsb;
-  const int s = sb * G + sg;
   const int64_t seg0 = (int64_t)s * U - half;
-  const bool active = s < nseg;
-  c32 *buf0 = lds[0][sg];
-  c32 *buf1 = lds[NB - 1][sg];
-  int cur = 0;
-
-  const int z0 = zg * zpb;
-  const int z1 = min(nz, z0 + zpb);
 
   c32 x[E];
   // stage 0 input: element n of butterfly b = t + j T sits at n * S0 + b
@@ -267,7 +254,7 @@ __global__ void __launch_bounds__(Gm::T *G) __attribute__((amdgpu_waves_per_eu(W
     // outputs: slot j*R0 + n holds index n * S0 + t + j T of the segment
     if (active) {
       constexpr int S0 = Gm::S(0), R0 = Gm::R[0];
-      float *prow = power + (int64_t)iz * ld;
+      float *prow = power + (int64_t)(iz - row_base) * ld;
 #pragma unroll
       for (int j = 0; j < Gm::B(0); ++j)
 #pragma unroll
@@ -283,6 +270,73 @@ __global__ void __launch_bounds__(Gm::T *G) __attribute__((amdgpu_waves_per_eu(W
   }
 }
 
+// Single spectrum: block -> (segment group, template group), template-group
+// major so concurrently running blocks share bank rows in L2.
+template <class Gm, int G, bool TWREG, bool PF, int WPE>
+__global__ void __launch_bounds__(Gm::T *G) __attribute__((amdgpu_waves_per_eu(WPE)))
+    ols_fp32_kernel(const c32 *__restrict__ spec, int64_t nbins, const c32 *__restrict__ bank,
+                    const c32 *__restrict__ tw, float *__restrict__ power, int64_t ld, int nseg,
+                    int U, int half, int nz, int zpb, int nsb) {
+  constexpr int T = Gm::T, NB = Gm::NBUF;
+  __shared__ c32 lds[NB][G][Gm::LP];
+  const int tid = threadIdx.x;
+  const int sg = tid / T;
+  const int t = tid % T;
+  const int sb = blockIdx.x % nsb;
+  const int zg = blockIdx.x / nsb;
+  const int s = sb * G + sg;
+  int cur = 0;
+  const int z0 = zg * zpb;
+  const int z1 = min(nz, z0 + zpb);
+  ols_unit<Gm, TWREG, PF>(spec, nbins, bank, tw, power, ld, s, s < nseg, U, half, z0, z1, 0,
+                          lds[0][sg], lds[NB - 1][sg], cur, t);
+}
+
+// Batch: persistent blocks take work items (series, template group, segment
+// group) from a device counter until the list is exhausted. Items are
+// numbered series by series (largest first on the host), template-group major
+// inside a series.
+template <class Gm, int G, bool TWREG, bool PF, int WPE>
+__global__ void __launch_bounds__(Gm::T *G) __attribute__((amdgpu_waves_per_eu(WPE)))
+    ols_fp32_batch_kernel(const SeriesDesc *__restrict__ desc, int nseries, int64_t total,
+                          unsigned long long *__restrict__ counter, const c32 *__restrict__ bank,
+                          const c32 *__restrict__ tw, int U, int half, int zpb) {
+  constexpr int T = Gm::T, NB = Gm::NBUF;
+  __shared__ c32 lds[NB][G][Gm::LP];
+  __shared__ long long s_item[2];
+  const int tid = threadIdx.x;
+  const int sg = tid / T;
+  const int t = tid % T;
+  int cur = 0, par = 0;
+  for (;;) {
+    if (tid == 0) s_item[par] = (long long)atomicAdd(counter, 1ULL);
+    __syncthreads();
+    const long long item = s_item[par];
+    par ^= 1;
+    if (item >= total) break;
+    // series k: the last with item_begin <= item
+    int lo = 0, hi = nseries - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (desc[mid].item_begin <= item) lo = mid;
+      else hi = mid - 1;
+    }
+    const SeriesDesc d = desc[lo];
+    const long long local = item - d.item_begin;
+    const int nsb = (d.nseg + G - 1) / G;
+    const int zg = (int)(local / nsb);
+    const int sb = (int)(local % nsb);
+    const int s = sb * G + sg;
+    const int z0 = d.row_off + zg * zpb;
+    const int z1 = min(d.row_off + d.nz, z0 + zpb);
+    ols_unit<Gm, TWREG, PF>(static_cast<const c32 *>(d.spec), d.nbins, bank, tw, d.power, d.ld,
+                            s, s < d.nseg, U, half, z0, z1, d.row_off, lds[0][sg], lds[NB - 1][sg],
+                            cur, t);
+  }
+}
+
+__global__ void reset_counter_kernel(unsigned long long *counter) { *counter = 0ULL; }
+
 // ---- variant registry ------------------------------------------------------
 
 template <class Gm, int G, bool TWREG, bool PF, int WPE>
@@ -295,6 +349,26 @@ static hipError_t launch_variant(const OlsArgs &a, hipStream_t st) {
                      static_cast<const c32 *>(a.bank), static_cast<const c32 *>(a.tw), a.power,
                      a.ld, a.nseg, a.U, a.half, a.nz, a.zpb, nsb);
   return hipGetLastError();
+}
+
+template <class Gm, int G, bool TWREG, bool PF, int WPE>
+static hipError_t launch_batch_variant(const BatchArgs &a, hipStream_t st) {
+  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, st, a.counter);
+  hipLaunchKernelGGL((ols_fp32_batch_kernel<Gm, G, TWREG, PF, WPE>), dim3((unsigned)a.grid),
+                     dim3(Gm::T * G), 0, st, a.desc, a.nseries, a.total, a.counter,
+                     static_cast<const c32 *>(a.bank), static_cast<const c32 *>(a.tw), a.U,
+                     a.half, a.zpb);
+  return hipGetLastError();
+}
+
+template <class Gm, int G, bool TWREG, bool PF, int WPE>
+static int batch_blocks_per_cu() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &nb, reinterpret_cast<const void *>(&ols_fp32_batch_kernel<Gm, G, TWREG, PF, WPE>),
+          Gm::T * G, 0) != hipSuccess)
+    return 0;
+  return nb;
 }
 
 template <class Gm, int G, bool TWREG, bool PF, int WPE = 1>
@@ -312,6 +386,8 @@ static constexpr OlsVariant make_variant(const char *name) {
   for (int i = 0; i < kMaxStages; ++i) v.lay.R[i] = i < Gm::P ? Gm::R[i] : 1;
   v.lds_bytes = Gm::NBUF * G * Gm::LP * 8;
   v.launch = &launch_variant<Gm, G, TWREG, PF, WPE>;
+  v.launch_batch = &launch_batch_variant<Gm, G, TWREG, PF, WPE>;
+  v.batch_blocks_per_cu = &batch_blocks_per_cu<Gm, G, TWREG, PF, WPE>;
   return v;
 }
 

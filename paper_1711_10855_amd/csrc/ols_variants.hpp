@@ -24,12 +24,38 @@ struct OlsArgs {
   int zpb;           // templates per work unit
 };
 
+// One series of a batch as the persistent kernel sees it.
+struct SeriesDesc {
+  const void *spec;     // complex64 [nbins]
+  float *power;         // [nz][ld]
+  int64_t nbins;
+  int64_t ld;
+  int64_t item_begin;   // first work item of this series
+  int nseg;             // segments
+  int nz;               // rows of this series' plane
+  int row_off;          // first bank row used by this series
+  int pad_;
+};
+
+struct BatchArgs {
+  const SeriesDesc *desc;
+  int nseries;
+  int64_t total;        // work items
+  unsigned long long *counter;
+  const void *bank;
+  const void *tw;
+  int U, half, zpb;
+  int grid;             // persistent blocks
+};
+
 struct OlsVariant {
   const char *name;
   int L, T, G, nbuf;
   LayoutDesc lay;
   int lds_bytes;
   hipError_t (*launch)(const OlsArgs &, hipStream_t);
+  hipError_t (*launch_batch)(const BatchArgs &, hipStream_t);
+  int (*batch_blocks_per_cu)();
 };
 
 const OlsVariant *fp32_variants(int *count);

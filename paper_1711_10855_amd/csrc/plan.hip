@@ -6,7 +6,11 @@
 #include <climits>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
+#include <cmath>
+#include <numeric>
 #include <string>
+#include <vector>
 
 #include "plan.hpp"
 
@@ -20,6 +24,14 @@ struct fdas_plan_s {
   size_t bank_bytes = 0;
   void *tw = nullptr;
   double plan_ms = 0.0;
+  // batched path
+  unsigned long long *counter = nullptr;
+  fdas::SeriesDesc *d_desc = nullptr;
+  size_t desc_cap = 0;
+  std::vector<fdas::SeriesDesc> last_desc;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t graph = nullptr;
+  int cus = 0;
 };
 
 namespace fdas {
@@ -79,6 +91,12 @@ int build_plan(fdas_plan_t *out, const fdas_params &p, int nz, int device, hipSt
   if (e == hipSuccess) e = hipMalloc(&pl->tw, (size_t)p.seg_len * 8);
   if (e != hipSuccess) {
     if (h) (void)hipFree(h);
+    destroy_plan(pl);
+    return set_error(FDAS_ERR_NOMEM, "plan allocation: %s", hipGetErrorString(e));
+  }
+  e = hipMalloc(reinterpret_cast<void **>(&pl->counter), 256);
+  if (e != hipSuccess) {
+    (void)hipFree(h);
     destroy_plan(pl);
     return set_error(FDAS_ERR_NOMEM, "plan allocation: %s", hipGetErrorString(e));
   }
@@ -167,18 +185,127 @@ int plan_convolve(fdas_plan_t pl, const void *spec, int64_t nbins, float *power,
   return FDAS_OK;
 }
 
+// Host side of the batched path: validate and order the series (largest
+// first), lay out their work items, upload the descriptors when the batch
+// changes, and replay one captured graph (counter reset + persistent kernel).
 int plan_convolve_batch(fdas_plan_t pl, const fdas_series *series, int nseries, hipStream_t s) {
-  (void)pl;
-  (void)series;
-  (void)nseries;
-  (void)s;
-  return set_error(FDAS_ERR_UNSUPPORTED, "batched correlation is not built yet");
+  const int G = pl->var->G;
+  const double dz = pl->p.dz;
+  std::vector<SeriesDesc> desc(nseries);
+  std::vector<double> cost(nseries);
+  for (int i = 0; i < nseries; ++i) {
+    const fdas_series &x = series[i];
+    if (!std::isfinite(x.zmax) || x.zmax < 0.0 || x.zmax > pl->p.zmax * (1.0 + 1e-12) + 1e-12)
+      return set_error(FDAS_ERR_INVALID, "series %d: zmax %g outside [0, %g]", i, x.zmax, pl->p.zmax);
+    const double off = (pl->p.zmax - x.zmax) / dz;
+    const double span = 2.0 * x.zmax / dz;
+    if (std::fabs(off - std::nearbyint(off)) > 1e-9 || std::fabs(span - std::nearbyint(span)) > 1e-9)
+      return set_error(FDAS_ERR_INVALID, "series %d: zmax %g is not on the plan's z grid", i, x.zmax);
+    const int64_t nseg = (x.nbins + pl->U - 1) / pl->U;
+    if (nseg > INT_MAX / 2) return set_error(FDAS_ERR_UNSUPPORTED, "series %d too long", i);
+    SeriesDesc &d = desc[i];
+    d.spec = x.spectrum;
+    d.power = x.power;
+    d.nbins = x.nbins;
+    d.ld = x.ld;
+    d.nseg = (int)nseg;
+    d.nz = (int)std::nearbyint(span) + 1;
+    d.row_off = (int)std::nearbyint(off);
+    d.pad_ = 0;
+    cost[i] = (double)d.nz * (double)x.nbins;
+  }
+  std::vector<int> order(nseries);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  std::vector<SeriesDesc> sorted(nseries);
+  int64_t total = 0;
+  for (int k = 0; k < nseries; ++k) {
+    sorted[k] = desc[order[k]];
+    sorted[k].item_begin = total;
+    const int64_t nsb = (sorted[k].nseg + G - 1) / G;
+    const int64_t nzg = (sorted[k].nz + pl->zpb - 1) / pl->zpb;
+    total += nsb * nzg;
+  }
+  if (total == 0) return FDAS_OK;
+
+  const bool same = pl->graph && sorted.size() == pl->last_desc.size() &&
+                    std::memcmp(sorted.data(), pl->last_desc.data(), sorted.size() * sizeof(SeriesDesc)) == 0;
+  hipError_t e = hipSuccess;
+  if (!same) {
+    // new batch layout: upload descriptors and capture a fresh graph
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_error(e, "synchronise before descriptor upload");
+    if (pl->graph) {
+      (void)hipGraphExecDestroy(pl->graph);
+      pl->graph = nullptr;
+    }
+    if (pl->desc_cap < sorted.size()) {
+      if (pl->d_desc) (void)hipFree(pl->d_desc);
+      pl->d_desc = nullptr;
+      pl->desc_cap = 0;
+      e = hipMalloc(&pl->d_desc, sorted.size() * sizeof(SeriesDesc));
+      if (e != hipSuccess) return set_error(FDAS_ERR_NOMEM, "descriptor allocation: %s", hipGetErrorString(e));
+      pl->desc_cap = sorted.size();
+    }
+    e = hipMemcpy(pl->d_desc, sorted.data(), sorted.size() * sizeof(SeriesDesc), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_error(e, "descriptor upload");
+    if (!pl->cap_stream) {
+      e = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking);
+      if (e != hipSuccess) return hip_error(e, "capture stream");
+    }
+    if (!pl->cus) {
+      e = hipDeviceGetAttribute(&pl->cus, hipDeviceAttributeMultiprocessorCount, pl->device);
+      if (e != hipSuccess) return hip_error(e, "CU count");
+    }
+    const int per_cu = std::max(1, pl->var->batch_blocks_per_cu());
+    BatchArgs a;
+    a.desc = pl->d_desc;
+    a.nseries = nseries;
+    a.total = total;
+    a.counter = pl->counter;
+    a.bank = pl->bank;
+    a.tw = pl->tw;
+    a.U = pl->U;
+    a.half = pl->m / 2;
+    a.zpb = pl->zpb;
+    a.grid = (int)std::min<int64_t>((int64_t)pl->cus * per_cu, total);
+    const char *nog = std::getenv("FDAS_NO_GRAPH");
+    if (nog && *nog == '1') {
+      e = pl->var->launch_batch(a, s);
+      if (e != hipSuccess) return hip_error(e, "batch kernel launch");
+      return FDAS_OK;  // nothing cached: the next call uploads again
+    }
+    hipGraph_t g = nullptr;
+    e = hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_error(e, "begin capture");
+    hipError_t le = pl->var->launch_batch(a, pl->cap_stream);
+    e = hipStreamEndCapture(pl->cap_stream, &g);
+    if (le != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return hip_error(le, "batch kernel capture");
+    }
+    if (e != hipSuccess) return hip_error(e, "end capture");
+    e = hipGraphInstantiate(&pl->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      pl->graph = nullptr;
+      return hip_error(e, "graph instantiate");
+    }
+    pl->last_desc = sorted;
+  }
+  e = hipGraphLaunch(pl->graph, s);
+  if (e != hipSuccess) return hip_error(e, "graph launch");
+  return FDAS_OK;
 }
 
 int destroy_plan(fdas_plan_t pl) {
   if (!pl) return FDAS_OK;
   hipError_t e = hipSuccess;
-  if (pl->bank || pl->tw) e = hipDeviceSynchronize();
+  if (pl->bank || pl->tw || pl->counter) e = hipDeviceSynchronize();
+  if (pl->graph) (void)hipGraphExecDestroy(pl->graph);
+  if (pl->cap_stream) (void)hipStreamDestroy(pl->cap_stream);
+  if (pl->d_desc) (void)hipFree(pl->d_desc);
+  if (pl->counter) (void)hipFree(pl->counter);
   if (pl->bank) (void)hipFree(pl->bank);
   if (pl->tw) (void)hipFree(pl->tw);
   delete pl;
