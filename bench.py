@@ -107,15 +107,16 @@ def main():
         return
 
     w = synth.WORKLOADS[args.workload]
-    if w.nseries != 1 or w.precision != "fp32":
-        raise SystemExit(f"workload {args.workload} is not a single-series FP32 workload")
-    seg_len = args.seg_len or w.seg_len
+    if w.nseries != 1:
+        raise SystemExit(f"workload {args.workload} is batched; single-series workloads only here")
+    prec = w.precision
+    seg_len = args.seg_len or (4096 if prec != "fp32" else w.seg_len)
     fdas.load()
-    a, _ = synth.single_series(args.workload)
+    a, _ = synth.single_series("fp32-paper" if args.workload == "mixed-paper" else args.workload)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     spec = torch.from_numpy(a).to(dev)
-    plan = fdas.Plan(w.zmax, w.dz, w.m, seg_len, "fp32", device=0)
+    plan = fdas.Plan(w.zmax, w.dz, w.m, seg_len, prec, device=0)
     info = plan.info
     nz, nbins = info.nz, spec.numel()
     out = torch.empty((nz, nbins), dtype=torch.float32, device=dev)
@@ -145,7 +146,8 @@ def main():
     traffic = traffic_from_profiles(info.kernel, args.workload)
 
     line = {
-        "metric": "z-r plane points/s (plain FP32, paper-scale workload); % of HBM roofline",
+        "metric": f"z-r plane points/s ({'plain FP32' if prec == 'fp32' else prec + ' MFMA'}, "
+                  f"paper-scale workload); % of HBM roofline",
         "value": value,
         "unit": "points/s",
         "n_gpus": 1,
@@ -155,7 +157,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if prec == "fp32" else f"{prec}+f32acc",
         "data": "synthetic",
         "config": {"workload": args.workload, "nbins": nbins, "nz": nz, "m": info.m,
                    "seg_len": info.seg_len, "zmax": w.zmax, "dz": w.dz,

@@ -379,6 +379,7 @@ static constexpr OlsVariant make_variant(const char *name) {
   v.T = Gm::T;
   v.G = G;
   v.nbuf = Gm::NBUF;
+  v.precision = 0;
   v.lay.L = Gm::L;
   v.lay.T = Gm::T;
   v.lay.E = Gm::E;

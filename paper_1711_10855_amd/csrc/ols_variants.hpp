@@ -22,6 +22,7 @@ struct OlsArgs {
   int half;          // m / 2
   int nz;            // rows to produce
   int zpb;           // templates per work unit
+  int bank_log2;     // mixed precision: the bank is stored times 2^bank_log2
 };
 
 // One series of a batch as the persistent kernel sees it.
@@ -51,6 +52,7 @@ struct BatchArgs {
 struct OlsVariant {
   const char *name;
   int L, T, G, nbuf;
+  int precision;     // FDAS_FP32 (0), FDAS_MIXED_FP16 (1), FDAS_MIXED_BF16 (2)
   LayoutDesc lay;
   int lds_bytes;
   hipError_t (*launch)(const OlsArgs &, hipStream_t);
@@ -59,6 +61,11 @@ struct OlsVariant {
 };
 
 const OlsVariant *fp32_variants(int *count);
+const OlsVariant *mixed_variants(int *count);
+hipError_t launch_bank_mixed(void *bank, const void *h, int nz, int m, int L, int precision,
+                             hipStream_t s);
+hipError_t launch_bank_mixed_natural(c32 *dst, const void *bank, int nz, int L, int precision,
+                                     hipStream_t s);
 
 hipError_t launch_templates(void *out, int nz, int m, double zmax, double dz, hipStream_t s);
 hipError_t launch_twiddles(c32 *tw, int L, hipStream_t s);

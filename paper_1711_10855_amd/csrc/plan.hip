@@ -37,16 +37,19 @@ struct fdas_plan_s {
 namespace fdas {
 
 bool mixed_supported(int seg_len) {
-  (void)seg_len;
+  int n = 0;
+  const OlsVariant *v = mixed_variants(&n);
+  for (int i = 0; i < n; ++i)
+    if (v[i].L == seg_len) return true;
   return false;
 }
 
-static const OlsVariant *find_variant(int L, const char *want) {
+static const OlsVariant *find_variant(int L, int precision, const char *want) {
   int n = 0;
-  const OlsVariant *v = fp32_variants(&n);
+  const OlsVariant *v = precision == FDAS_FP32 ? fp32_variants(&n) : mixed_variants(&n);
   const OlsVariant *first = nullptr;
   for (int i = 0; i < n; ++i) {
-    if (v[i].L != L) continue;
+    if (v[i].L != L || v[i].precision != precision) continue;
     if (want && *want && std::strcmp(v[i].name, want) == 0) return &v[i];
     if (!first) first = &v[i];
   }
@@ -62,7 +65,7 @@ static int default_zpb(int nz) {
 int build_plan(fdas_plan_t *out, const fdas_params &p, int nz, int device, hipStream_t s) {
   const auto t0 = std::chrono::steady_clock::now();
   const char *want = std::getenv("FDAS_VARIANT");
-  const OlsVariant *var = find_variant(p.seg_len, want);
+  const OlsVariant *var = find_variant(p.seg_len, p.precision, want);
   if (!var) {
     if (want && *want)
       return set_error(FDAS_ERR_UNSUPPORTED, "variant '%s' not compiled for seg_len %d", want, p.seg_len);
@@ -85,7 +88,7 @@ int build_plan(fdas_plan_t *out, const fdas_params &p, int nz, int device, hipSt
 
   void *h = nullptr;
   const size_t hbytes = (size_t)nz * (p.m + 1) * 16;
-  pl->bank_bytes = (size_t)nz * p.seg_len * 8;
+  pl->bank_bytes = (size_t)nz * p.seg_len * (p.precision == FDAS_FP32 ? 8 : 4);
   hipError_t e = hipMalloc(&h, hbytes);
   if (e == hipSuccess) e = hipMalloc(&pl->bank, pl->bank_bytes);
   if (e == hipSuccess) e = hipMalloc(&pl->tw, (size_t)p.seg_len * 8);
@@ -101,7 +104,12 @@ int build_plan(fdas_plan_t *out, const fdas_params &p, int nz, int device, hipSt
     return set_error(FDAS_ERR_NOMEM, "plan allocation: %s", hipGetErrorString(e));
   }
   e = launch_templates(h, nz, p.m, p.zmax, p.dz, s);
-  if (e == hipSuccess) e = launch_bank(static_cast<c32 *>(pl->bank), h, nz, p.m, var->lay, s);
+  if (e == hipSuccess) {
+    if (p.precision == FDAS_FP32)
+      e = launch_bank(static_cast<c32 *>(pl->bank), h, nz, p.m, var->lay, s);
+    else
+      e = launch_bank_mixed(pl->bank, h, nz, p.m, p.seg_len, p.precision, s);
+  }
   if (e == hipSuccess) e = launch_twiddles(static_cast<c32 *>(pl->tw), p.seg_len, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   (void)hipFree(h);
@@ -131,12 +139,14 @@ void plan_info(fdas_plan_t pl, fdas_plan_info *info) {
 }
 
 int list_variants(int seg_len, int precision, char *buf, size_t len) {
-  int n = 0, count = 0;
-  const OlsVariant *v = fp32_variants(&n);
+  int count = 0;
   std::string out;
-  if (precision == -1 || precision == FDAS_FP32) {
+  for (int pass = 0; pass < 2; ++pass) {
+    int n = 0;
+    const OlsVariant *v = pass == 0 ? fp32_variants(&n) : mixed_variants(&n);
     for (int i = 0; i < n; ++i) {
       if (seg_len && v[i].L != seg_len) continue;
+      if (precision != -1 && v[i].precision != precision) continue;
       out += v[i].name;
       out += '\n';
       ++count;
@@ -154,8 +164,12 @@ int plan_seg_len(fdas_plan_t pl) { return pl->L; }
 int plan_device(fdas_plan_t pl) { return pl->device; }
 
 int plan_bank_natural(fdas_plan_t pl, void *dst, hipStream_t s) {
-  hipError_t e = launch_bank_natural(static_cast<c32 *>(dst), static_cast<const c32 *>(pl->bank),
-                                     pl->nz, pl->var->lay, s);
+  hipError_t e = pl->p.precision == FDAS_FP32
+                     ? launch_bank_natural(static_cast<c32 *>(dst),
+                                           static_cast<const c32 *>(pl->bank), pl->nz,
+                                           pl->var->lay, s)
+                     : launch_bank_mixed_natural(static_cast<c32 *>(dst), pl->bank, pl->nz, pl->L,
+                                                 pl->p.precision, s);
   if (e != hipSuccess) return hip_error(e, "bank copy kernel");
   return FDAS_OK;
 }
@@ -180,6 +194,8 @@ int plan_convolve(fdas_plan_t pl, const void *spec, int64_t nbins, float *power,
   a.half = pl->m / 2;
   a.nz = pl->nz;
   a.zpb = pl->zpb;
+  a.bank_log2 = 0;
+  while ((1 << a.bank_log2) < pl->L) ++a.bank_log2;
   hipError_t e = pl->var->launch(a, s);
   if (e != hipSuccess) return hip_error(e, "correlation kernel launch");
   return FDAS_OK;
@@ -189,6 +205,8 @@ int plan_convolve(fdas_plan_t pl, const void *spec, int64_t nbins, float *power,
 // first), lay out their work items, upload the descriptors when the batch
 // changes, and replay one captured graph (counter reset + persistent kernel).
 int plan_convolve_batch(fdas_plan_t pl, const fdas_series *series, int nseries, hipStream_t s) {
+  if (!pl->var->launch_batch)
+    return set_error(FDAS_ERR_UNSUPPORTED, "kernel %s has no batched form", pl->var->name);
   const int G = pl->var->G;
   const double dz = pl->p.dz;
   std::vector<SeriesDesc> desc(nseries);

@@ -1,0 +1,91 @@
+"""Mixed-precision path (16-bit storage, MFMA DFT stages, FP32 accumulation)
+against the FP64 oracle through the C ABI. Bar: max |P - P_ref| <= 1e-3 *
+max(P_ref); the measured error is printed for every case."""
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1711_10855_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL_MIXED = 1e-3
+
+
+def to_dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex64)).cuda()
+
+
+def rel_err(p, ref):
+    return float(np.max(np.abs(p.astype(np.float64) - ref)) / np.max(ref))
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_mixed_bank_matches_oracle(gpu, prec):
+    with gpu.Plan(100.0, 2.0, 256, 4096, prec) as p:
+        dev = p.bank().cpu().numpy().astype(np.complex128)
+    _, h = oracle.templates64(100.0, 2.0, 256)
+    ref = oracle.bank_natural(h, 256, 4096)
+    err = float(np.max(np.abs(dev - ref)) / np.max(np.abs(ref)))
+    print(f"{prec} bank max rel err {err:.2e}")
+    assert err <= (1e-3 if prec == "fp16" else 8e-3)
+
+
+@pytest.mark.parametrize("prec,nbins,zmax,m", [
+    ("fp16", 3 * 3840 + 517, 10.0, 256),
+    ("fp16", 1000, 6.0, 256),
+    ("fp16", 20000, 30.0, 512),
+])
+def test_mixed_full_plane(gpu, prec, nbins, zmax, m):
+    a = synth.small_random_spectrum(nbins, seed=nbins)
+    ref = oracle.plane_direct(a, zmax, 2.0, m)
+    print(f"{prec} nbins={nbins} zmax={zmax} m={m}", flush=True)
+    out = gpu.convolve(to_dev(a), zmax, 2.0, m, 4096, prec).cpu().numpy()
+    err = rel_err(out, ref)
+    print(f"{prec} nbins={nbins}: max|dP|/maxP = {err:.3e}")
+    assert err <= TOL_MIXED
+
+
+def test_mixed_bf16_error_is_reported(gpu):
+    """BF16 storage without split products: 8 mantissa bits. The measured
+    error is recorded; the 1e-3 bar applies to the split form."""
+    a = synth.small_random_spectrum(12000, seed=77)
+    ref = oracle.plane_direct(a, 10.0, 2.0, 256)
+    out = gpu.convolve(to_dev(a), 10.0, 2.0, 256, 4096, "bf16").cpu().numpy()
+    err = rel_err(out, ref)
+    print(f"bf16 (no split) max|dP|/maxP = {err:.3e}")
+    assert err <= 2e-2
+
+
+def test_mixed_zero_and_scaled_inputs(gpu):
+    import torch
+    z = torch.zeros(9000, dtype=torch.complex64, device="cuda")
+    out = gpu.convolve(z, 10.0, 2.0, 256, 4096, "fp16")
+    assert float(out.abs().max()) == 0.0
+    # per-segment power-of-two scaling: results scale exactly with the input
+    a = synth.small_random_spectrum(9000, seed=5)
+    p1 = gpu.convolve(to_dev(a), 10.0, 2.0, 256, 4096, "fp16").cpu().numpy()
+    p2 = gpu.convolve(to_dev(a * 1024.0), 10.0, 2.0, 256, 4096, "fp16").cpu().numpy()
+    assert np.array_equal(p1 * (1024.0 ** 2), p2)
+    p3 = gpu.convolve(to_dev(a * 1e-12), 10.0, 2.0, 256, 4096, "fp16").cpu().numpy()
+    ref = oracle.plane_direct(a.astype(np.complex128) * 1e-12, 10.0, 2.0, 256)
+    assert rel_err(p3, ref) <= TOL_MIXED
+
+
+def test_mixed_workload_sampled_points(gpu):
+    """Paper-scale inputs (2^21 bins, nz 101, m 256) through the FP16 MFMA path."""
+    a, chirps = synth.single_series("fp32-paper")
+    p = gpu.convolve(to_dev(a), 100.0, 2.0, 256, 4096, "fp16").cpu().numpy()
+    nz, nbins = p.shape
+    rng = np.random.default_rng(12)
+    iz = rng.integers(0, nz, 5000)
+    r = rng.integers(0, nbins, 5000)
+    extra = np.array([0, 1, nbins - 1] + [int(round(c.r0)) for c in chirps])
+    iz = np.concatenate([iz, np.repeat(np.arange(nz), extra.size)])
+    r = np.concatenate([r, np.tile(extra, nz)])
+    ref = oracle.plane_points(a, 100.0, 2.0, 256, iz, r)
+    err = float(np.max(np.abs(p[iz, r] - ref)) / ref.max())
+    print(f"mixed-paper fp16 sampled max|dP|/maxP = {err:.3e}")
+    assert err <= TOL_MIXED
