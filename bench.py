@@ -2,17 +2,23 @@
 
 A step is one call of the hot path (segment load, forward FFT, per-template
 product + inverse FFT, overlap discard, |.|^2 store) over the whole input of
-the workload: by default the paper-scale plain-FP32 workload (2^21 bins,
-z in [-100, 100] step 2 -> 101 templates of width 256, segment FFT 2048),
-producing the 101 x 2^21 FP32 power plane (847 MB). Inputs are resident in
-device memory before the timed region; the plan (templates, bank) is built
-once outside it and its time is reported separately.
+the workload. The default workload is the paper-scale plain-FP32 one (2^21
+bins, z in [-100, 100] step 2 -> 101 templates of width 256, segment FFT
+2048) producing the 101 x 2^21 FP32 power plane (847 MB). Inputs are resident
+in device memory before the timed region; the plan (templates, bank) is
+built once outside it and its time is reported separately. The same run also
+times the FP16 matrix-core form on the same input ("compare").
+
+Other workloads (--workload): fp32-small, mixed-paper, batch-fp32 (512 series
+of uneven length, per-series zmax, one graph-captured launch per wave),
+batch-mixed-wide (256 series, z in [-200, 200], m 512, run in waves that fit
+device memory).
 
 Prints ONE JSON line. `value` is z-r plane points per second; `roofline`
-prices the dominant kernel's algorithmic bytes per launch
-(4 B per plane point written + 8 B per input bin read) against the 8 TB/s
-HBM peak, with the kernel duration measured by HIP events on the stream the
-kernel runs on; `cpu_baseline` times the FP64 oracle on a bounded sample.
+prices the dominant kernel's algorithmic bytes per launch (4 B per plane
+point written + 8 B per input bin read) against the 8 TB/s HBM peak, with
+the kernel time measured by HIP events on the stream the kernel runs on;
+`cpu_baseline` times the FP64 oracle on a bounded sample of the same input.
 """
 
 from __future__ import annotations
@@ -38,9 +44,14 @@ def parse():
     ap.add_argument("--workload", default="fp32-paper")
     ap.add_argument("--variant", default=None, help="force a compiled kernel variant")
     ap.add_argument("--zpb", type=int, default=None, help="templates per work unit")
+    ap.add_argument("--precision", default=None, help="override the workload precision")
+    ap.add_argument("--seg-len", type=int, default=None)
+    ap.add_argument("--nseries", type=int, default=None, help="batched: first N series only")
+    ap.add_argument("--wave-gb", type=float, default=100.0,
+                    help="batched: device memory budget for the planes of one wave")
+    ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-bins", type=int, default=1 << 20)
-    ap.add_argument("--seg-len", type=int, default=None)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (for "
                          "scaling HBM byte counters) and exit")
@@ -65,19 +76,109 @@ def traffic_from_profiles(kernel: str, workload: str):
     return None
 
 
-def cpu_baseline(a, w, sample_bins: int):
+def cpu_baseline(a, zmax, dz, m, nz, sample_bins: int):
     """The FP64 oracle (unchanged) on the first `sample_bins` bins, all rows."""
     import numpy as np
 
     import oracle
     sample = np.ascontiguousarray(a[:sample_bins])
     t0 = time.perf_counter()
-    p = oracle.plane_direct(sample, w.zmax, w.dz, w.m)
+    p = oracle.plane_direct(sample, zmax, dz, m)
     dt = time.perf_counter() - t0
     pts = p.shape[0] * p.shape[1]
     return {"value": pts / dt, "unit": "points/s", "cores": 1, "kind": "oracle",
-            "sample": f"{w.nz} rows x first {sample_bins} bins of the same spectrum "
+            "sample": f"{nz} rows x first {sample_bins} bins of the input spectrum "
                       f"({pts} points, {dt:.1f} s, single process NumPy FP64 direct sum)"}
+
+
+def _time(fn, steps, warmup, stream):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record(stream)
+    for _ in range(steps):
+        fn()
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return start.elapsed_time(stop) / steps, wall
+
+
+def run_single(a_dev, zmax, dz, m, seg_len, prec, steps, warmup):
+    """Time fdas_convolve on one resident spectrum; returns a result dict."""
+    import torch
+
+    from paper_1711_10855_amd import fdas
+    plan = fdas.Plan(zmax, dz, m, seg_len, prec, device=0)
+    info = plan.info
+    nz, nbins = info.nz, a_dev.numel()
+    out = torch.empty((nz, nbins), dtype=torch.float32, device=a_dev.device)
+    stream = torch.cuda.current_stream(a_dev.device)
+    ms, wall = _time(lambda: plan.convolve(a_dev, out=out), steps, warmup, stream)
+    plan.close()
+    del out
+    points = nz * nbins
+    bytes_launch = 4.0 * points + 8.0 * nbins
+    return {"points": points, "nz": nz, "nbins": nbins, "ms": ms, "wall": wall,
+            "value": points / (ms * 1e-3), "bytes_launch": bytes_launch,
+            "achieved": bytes_launch / (ms * 1e-3) / 1e9, "info": info}
+
+
+def run_batch(name, prec, seg_len, nseries, steps, warmup, wave_bytes):
+    """Time fdas_convolve_batch over a batched workload, in waves that fit."""
+    import numpy as np
+    import torch
+
+    from paper_1711_10855_amd import fdas, synth
+    w = synth.WORKLOADS[name]
+    t0 = time.perf_counter()
+    specs, spectra = synth.batch_inputs(name, nseries)
+    gen_s = time.perf_counter() - t0
+    dev = torch.device("cuda:0")
+    spec_dev = [torch.from_numpy(a).to(dev) for a in spectra]
+    plan = fdas.Plan(w.zmax, w.dz, w.m, seg_len, prec, device=0)
+    info = plan.info
+    rows = [int(round(2 * sp.zmax / w.dz)) + 1 for sp in specs]
+    sizes = [r * sp.nbins * 4 for r, sp in zip(rows, specs)]
+    # waves: consecutive series whose planes fit the budget
+    waves, cur, acc = [], [], 0
+    for i, b in enumerate(sizes):
+        if cur and acc + b > wave_bytes:
+            waves.append(cur)
+            cur, acc = [], 0
+        cur.append(i)
+        acc += b
+    if cur:
+        waves.append(cur)
+    buf = torch.empty(max(sum(sizes[i] for i in wv) for wv in waves) // 4,
+                      dtype=torch.float32, device=dev)
+    calls = []
+    for wv in waves:
+        outs, off = [], 0
+        for i in wv:
+            outs.append(buf[off:off + rows[i] * specs[i].nbins].view(rows[i], specs[i].nbins))
+            off += rows[i] * specs[i].nbins
+        calls.append(([spec_dev[i] for i in wv], [specs[i].zmax for i in wv], outs))
+
+    def step():
+        for sp, zm, outs in calls:
+            plan.convolve_batch(sp, zm, outs)
+
+    stream = torch.cuda.current_stream(dev)
+    ms, wall = _time(step, steps, warmup, stream)
+    plan.close()
+    points = int(sum(r * sp.nbins for r, sp in zip(rows, specs)))
+    nbins_total = int(sum(sp.nbins for sp in specs))
+    bytes_launch = 4.0 * points + 8.0 * nbins_total
+    a0 = spectra[int(np.argmax([sp.nbins for sp in specs]))]
+    return {"points": points, "nseries": len(specs), "waves": len(waves), "ms": ms,
+            "wall": wall, "value": points / (ms * 1e-3), "bytes_launch": bytes_launch,
+            "achieved": bytes_launch / (ms * 1e-3) / 1e9, "info": info, "gen_s": gen_s,
+            "sample_spectrum": a0, "zmax": w.zmax, "dz": w.dz, "m": w.m}
 
 
 def main():
@@ -91,7 +192,6 @@ def main():
     if args.zpb:
         os.environ["FDAS_ZPB"] = str(args.zpb)
 
-    import numpy as np
     import torch
 
     from paper_1711_10855_amd import fdas, synth
@@ -106,72 +206,66 @@ def main():
         print(json.dumps({"calibrate_copy_bytes": n, "launches": 3}))
         return
 
-    w = synth.WORKLOADS[args.workload]
-    if w.nseries != 1:
-        raise SystemExit(f"workload {args.workload} is batched; single-series workloads only here")
-    prec = w.precision
-    seg_len = args.seg_len or (4096 if prec != "fp32" else w.seg_len)
     fdas.load()
-    a, _ = synth.single_series("fp32-paper" if args.workload == "mixed-paper" else args.workload)
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    spec = torch.from_numpy(a).to(dev)
-    plan = fdas.Plan(w.zmax, w.dz, w.m, seg_len, prec, device=0)
-    info = plan.info
-    nz, nbins = info.nz, spec.numel()
-    out = torch.empty((nz, nbins), dtype=torch.float32, device=dev)
-    stream = torch.cuda.current_stream(dev)
-
-    for _ in range(args.warmup):
-        plan.convolve(spec, out=out)
-    torch.cuda.synchronize(dev)
-
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize(dev)
-    t0 = time.perf_counter()
-    start.record(stream)
-    for _ in range(args.steps):
-        plan.convolve(spec, out=out)
-    stop.record(stream)
-    torch.cuda.synchronize(dev)
-    wall = time.perf_counter() - t0
-    ms_total = start.elapsed_time(stop)
-    ms_step = ms_total / args.steps
-
-    points = nz * nbins
-    value = points / (ms_step * 1e-3)
-    bytes_launch = 4.0 * points + 8.0 * nbins
-    achieved = bytes_launch / (ms_step * 1e-3) / 1e9
+    torch.cuda.set_device(0)
+    w = synth.WORKLOADS[args.workload]
+    prec = args.precision or w.precision
+    compare = None
+    if w.nseries == 1:
+        seg_len = args.seg_len or (4096 if prec != "fp32" else w.seg_len)
+        src = "fp32-paper" if args.workload == "mixed-paper" else args.workload
+        a, _ = synth.single_series(src)
+        a_dev = torch.from_numpy(a).to("cuda:0")
+        r = run_single(a_dev, w.zmax, w.dz, w.m, seg_len, prec, args.steps, args.warmup)
+        if not args.no_compare and prec == "fp32" and not args.variant and w.m < 4096:
+            c = run_single(a_dev, w.zmax, w.dz, w.m, 4096, "fp16", args.steps, args.warmup)
+            compare = {"fp16_mfma": {
+                "value": c["value"], "ms_per_step": c["ms"], "seg_len": 4096,
+                "kernel": c["info"].kernel, "frac": c["achieved"] / HBM_PEAK_GBS,
+                "speedup_vs_fp32": c["value"] / r["value"],
+                "error_bar": "max|P-P_ref| <= 1e-3 max P_ref (tested)"}}
+        cpu_in = (a, w.zmax, w.dz, w.m, r["nz"])
+        cfg = {"workload": args.workload, "nbins": r["nbins"], "nz": r["nz"]}
+    else:
+        seg_len = args.seg_len or (4096 if prec != "fp32" else w.seg_len)
+        r = run_batch(args.workload, prec, seg_len, args.nseries, args.steps, args.warmup,
+                      int(args.wave_gb * 1e9))
+        cpu_in = (r["sample_spectrum"], r["zmax"], r["dz"], r["m"], r["info"].nz)
+        cfg = {"workload": args.workload, "nseries": r["nseries"], "waves": r["waves"],
+               "input_gen_s": round(r["gen_s"], 1)}
+    info = r["info"]
+    cfg.update({"m": info.m, "seg_len": info.seg_len, "zmax": w.zmax, "dz": w.dz,
+                "precision": prec, "kernel": info.kernel,
+                "templates_per_block": info.templates_per_block,
+                "plan_ms": round(info.plan_ms, 3), "wall_s_timed": round(r["wall"], 4)})
     traffic = traffic_from_profiles(info.kernel, args.workload)
-
+    label = ("plain FP32" if prec == "fp32"
+             else f"{prec} storage, MFMA DFT stages, FP32 accumulation")
     line = {
-        "metric": f"z-r plane points/s ({'plain FP32' if prec == 'fp32' else prec + ' MFMA'}, "
-                  f"paper-scale workload); % of HBM roofline",
-        "value": value,
+        "metric": f"z-r plane points/s ({label}); % of HBM roofline",
+        "value": r["value"],
         "unit": "points/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": r["ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32" if prec == "fp32" else f"{prec}+f32acc",
         "data": "synthetic",
-        "config": {"workload": args.workload, "nbins": nbins, "nz": nz, "m": info.m,
-                   "seg_len": info.seg_len, "zmax": w.zmax, "dz": w.dz,
-                   "kernel": info.kernel, "templates_per_block": info.templates_per_block,
-                   "plan_ms": round(info.plan_ms, 3), "wall_s_timed": round(wall, 4)},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "bytes_per_point": bytes_launch / points},
+        "config": cfg,
+        "roofline": {"bound": "hbm", "achieved": r["achieved"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": r["achieved"] / HBM_PEAK_GBS, "traffic": traffic,
+                     "bytes_per_point": r["bytes_launch"] / r["points"]},
         "cpu_baseline": None,
     }
-    plan.close()
-    del out
+    if compare:
+        line["compare"] = compare
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(a, w, min(args.cpu_sample_bins, nbins))
+        a0, zmax, dz, m, nz = cpu_in
+        line["cpu_baseline"] = cpu_baseline(a0, zmax, dz, m, nz,
+                                            min(args.cpu_sample_bins, a0.size))
     print(json.dumps(line))
 
 

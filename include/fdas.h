@@ -56,7 +56,11 @@ extern "C" {
 
 /* ---- flags ----------------------------------------------------------------- */
 #define FDAS_FLAG_SPLIT 1u    /* mixed: hi+lo split products (3 MFMA per stage) */
-#define FDAS_FLAG_AUTOTUNE 2u /* fdas_plan: time the candidate kernels, keep best */
+#define FDAS_FLAG_AUTOTUNE 2u /* fdas_plan: time the compiled variants (segment
+                                 length, radix split, threads, templates per
+                                 block) on a synthetic spectrum of 2^20 bins and
+                                 keep the fastest per plane point; cached in the
+                                 file named by FDAS_TUNE_CACHE when set */
 
 /* Filter-bank parameters.
  *   zmax, dz  : z grid z_i = -zmax + i*dz; zmax >= 0, dz > 0, 2*zmax/dz an
@@ -64,8 +68,10 @@ extern "C" {
  *   m         : even, >= 2; taps q in [-m/2, m/2] (m + 1 bins, eq. 2).
  *               0 selects the default nextpow2(2*zmax + 32), at least 8.
  *   seg_len   : overlap-and-save segment (FFT) length L, a power of two in
- *               [256, 16384] with L > m. 0 selects the default (from the
- *               autotune cache if one is loaded, else min 8*m clamped).
+ *               [256, 16384] with L > m (mixed precisions: 4096). 0 selects
+ *               the default (FP32: nextpow2(8 m) clamped to [256, 16384];
+ *               mixed: 4096), or with FDAS_FLAG_AUTOTUNE lets the tuner
+ *               choose among compiled lengths with L - m >= L / 2.
  *   precision : FDAS_FP32 / FDAS_MIXED_FP16 / FDAS_MIXED_BF16.
  *   flags     : FDAS_FLAG_* bits.                                           */
 typedef struct {

@@ -66,8 +66,14 @@ int resolve_params(const fdas_params *in, fdas_params *out, int *nz_out) {
   }
   if (p.m < 2 || (p.m & 1)) return set_error(FDAS_ERR_INVALID, "m must be even and >= 2 (m=%d)", p.m);
   if (p.m > 8192) return set_error(FDAS_ERR_UNSUPPORTED, "m=%d exceeds the largest segment", p.m);
-  if (p.seg_len == 0) p.seg_len = default_seg_len(p.m, nz, p.precision);
   if (p.seg_len < 0) return set_error(FDAS_ERR_INVALID, "seg_len must be >= 0");
+  if (p.seg_len == 0 && (p.flags & FDAS_FLAG_AUTOTUNE)) {
+    // the autotuner picks a compiled length with L - m >= L / 2
+    *out = p;
+    if (nz_out) *nz_out = nz;
+    return FDAS_OK;
+  }
+  if (p.seg_len == 0) p.seg_len = default_seg_len(p.m, nz, p.precision);
   if (p.seg_len <= p.m)
     return set_error(FDAS_ERR_INVALID, "seg_len (%d) must exceed m (%d)", p.seg_len, p.m);
   if ((p.seg_len & (p.seg_len - 1)) || p.seg_len < 256 || p.seg_len > 16384)
@@ -83,7 +89,7 @@ int resolve_params(const fdas_params *in, fdas_params *out, int *nz_out) {
 
 int default_seg_len(int m, int nz, int precision) {
   (void)nz;
-  (void)precision;
+  if (precision != FDAS_FP32) return 4096;  // the compiled matrix-core length
   int L = next_pow2(8.0 * m);
   if (L < 256) L = 256;
   if (L > 16384) L = 16384;

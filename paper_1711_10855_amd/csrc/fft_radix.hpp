@@ -141,6 +141,15 @@ __device__ __forceinline__ void dft16(c32 *v) {
   t = v[11]; v[11] = v[14]; v[14] = t;
 }
 
+// The pointer value passes through an empty asm statement, so loads through
+// it cannot be hoisted out of the loop the call sits in (keeps loop-invariant
+// table reads inside persistent loops instead of pinning them in registers).
+template <class T>
+__device__ __forceinline__ T *opaque_ptr(T *p) {
+  asm volatile("" : "+s"(p));
+  return p;
+}
+
 template <int DIR, int R>
 __device__ __forceinline__ void dft(c32 *v) {
   static_assert(R == 2 || R == 4 || R == 8 || R == 16, "radix");

@@ -329,9 +329,9 @@ __global__ void __launch_bounds__(Gm::T *G) __attribute__((amdgpu_waves_per_eu(W
     const int s = sb * G + sg;
     const int z0 = d.row_off + zg * zpb;
     const int z1 = min(d.row_off + d.nz, z0 + zpb);
-    ols_unit<Gm, TWREG, PF>(static_cast<const c32 *>(d.spec), d.nbins, bank, tw, d.power, d.ld,
-                            s, s < d.nseg, U, half, z0, z1, d.row_off, lds[0][sg], lds[NB - 1][sg],
-                            cur, t);
+    ols_unit<Gm, TWREG, PF>(static_cast<const c32 *>(d.spec), d.nbins, opaque_ptr(bank),
+                            opaque_ptr(tw), d.power, d.ld, s, s < d.nseg, U, half, z0, z1,
+                            d.row_off, lds[0][sg], lds[NB - 1][sg], cur, t);
   }
 }
 

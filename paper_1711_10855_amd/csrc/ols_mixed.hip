@@ -67,36 +67,16 @@ struct Vec<__bf16> {
 // writes of 4 values by rows 16 apart are then free of bank conflicts.
 constexpr int kPlane = 256 * 16 + 16 * 8;  // halves per plane
 
+// Plan-time constants of the L = 4096 mixed kernel (bytes):
+//   [17 matrices][64 lanes][B1, B2][8 x 16-bit]  matrix 0: plain inverse DFT16,
+//                                                 matrix 1 + n1: w256^(n1 k0) folded in
+//   then FP32 complex twiddles: [64 lanes][4] w256^((4g+i) c)
+//                               [16 tiles][64 lanes][4] w4096^((4g+i) n2)
+constexpr int kConstB = 17 * 64 * 2 * 16;
+constexpr int kConstBytes = kConstB + (64 * 4 + 16 * 64 * 4) * 8;
+
 __device__ __forceinline__ int lds_idx(int row, int e) {
   return row * 16 + (row >> 4) * 8 + ((((e >> 3) ^ (row >> 3)) & 1) << 3) + (e & 7);
-}
-
-// exp(+2 pi i num / den) in FP32 for 0 <= num < den (den a power of two)
-__device__ __forceinline__ c32 wpos(int num, int den) {
-  float s, c;
-  sincospif(2.0f * (float)num / (float)den, &s, &c);
-  return {c, s};
-}
-
-// Real-form B operand of lane l for the 16-point matrix M[c][k] = exp(2 pi i
-// k (16 c + phase) / 256): re (B1 = [Re M | -Im M]) and im (B2 = [Im M | Re M]).
-template <class H>
-__device__ __forceinline__ void make_b(int lane, int phase, typename Vec<H>::v8 &b1,
-                                       typename Vec<H>::v8 &b2) {
-  const int c = lane & 15, kg = lane >> 4;
-#pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const int kk = kg * 8 + j;  // 0..31
-    const int k = kk & 15;
-    const c32 w = wpos((k * (16 * c + phase)) & 255, 256);
-    if (kk < 16) {
-      b1[j] = (H)w.x;
-      b2[j] = (H)w.y;
-    } else {
-      b1[j] = (H)(-w.y);
-      b2[j] = (H)w.x;
-    }
-  }
 }
 
 template <class H>
@@ -122,65 +102,108 @@ __device__ __forceinline__ int fwd_addr(int t, int n) {
 }
 __device__ __forceinline__ int fpad(int a) { return a + (a >> 4); }
 
-template <class H, bool PF, bool NT>
-__global__ void __launch_bounds__(256)
-    ols_mixed4096_kernel(const c32 *__restrict__ spec, int64_t nbins, const H *__restrict__ bank,
-                         const c32 *__restrict__ tw, float *__restrict__ power, int64_t ld,
-                         int nseg, int U, int half, int nz, int zpb, int nsb, int bank_log2) {
+constexpr int kMixF32 = (4096 + 4096 / 16) * 8;
+constexpr int kMix16 = 3 * 2 * kPlane * 2;
+constexpr int kMixSmem = kMixF32 > kMix16 ? kMixF32 : kMix16;
+
+// Per-lane constants, loaded once per block from the plan-time table.
+template <class H, int NW>
+struct MixedConsts {
+  static constexpr int TPW = 16 / NW;
+  typename Vec<H>::v8 bF1, bF2;            // plain inverse DFT16
+  typename Vec<H>::v8 bT1[TPW], bT2[TPW];  // stage 0' tiles n1 = TPW w + j
+  c32 tw1[4];                              // after stage 2': w256^((4g+i) c)
+  c32 tw2[TPW][4];                         // after stage 1': w4096^((4g+i) n2)
+};
+
+template <class H, int NW>
+__device__ __forceinline__ void load_mixed_consts(MixedConsts<H, NW> &K,
+                                                  const unsigned char *__restrict__ consts,
+                                                  int lane, int w) {
+  typedef typename Vec<H>::v8 v8;
+  constexpr int TPW = 16 / NW;
+  const v8 *cb = reinterpret_cast<const v8 *>(consts);
+  K.bF1 = cb[(0 * 64 + lane) * 2];
+  K.bF2 = cb[(0 * 64 + lane) * 2 + 1];
+#pragma unroll
+  for (int j = 0; j < TPW; ++j) {
+    K.bT1[j] = cb[((1 + TPW * w + j) * 64 + lane) * 2];
+    K.bT2[j] = cb[((1 + TPW * w + j) * 64 + lane) * 2 + 1];
+  }
+  const c32 *ctw = reinterpret_cast<const c32 *>(consts + kConstB);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    K.tw1[i] = ctw[lane * 4 + i];
+#pragma unroll
+    for (int j = 0; j < TPW; ++j) K.tw2[j][i] = ctw[256 + ((TPW * w + j) * 64 + lane) * 4 + i];
+  }
+}
+
+// One work unit of the mixed kernel: segment s, bank rows [z0, z1), plane
+// rows iz - row_base. Every thread of the block calls it (barriers inside).
+template <class H, bool PF, bool NT, int NW>
+__device__ __forceinline__ void mixed_unit(const MixedConsts<H, NW> &K,
+                                           const c32 *__restrict__ spec, int64_t nbins,
+                                           const H *__restrict__ bank, const c32 *__restrict__ tw,
+                                           float *__restrict__ power, int64_t ld, int s,
+                                           bool active, int U, int half, int z0, int z1,
+                                           int row_base, int bank_log2, unsigned char *smem,
+                                           float *s_max) {
   typedef typename Vec<H>::v8 v8;
   constexpr int L = 4096;
-  // LDS: the FP32 forward exchange buffer is dead once X is written, so it
-  // shares storage with the three 16-bit buffers (X, Ea, Eb).
-  constexpr int kF32 = (L + L / 16) * 8;
-  constexpr int k16 = 3 * 2 * kPlane * 2;
-  __shared__ __attribute__((aligned(16))) unsigned char smem[kF32 > k16 ? kF32 : k16];
-  __shared__ float s_max[4];
+  constexpr int TPW = 16 / NW;
   c32 *fbuf = reinterpret_cast<c32 *>(smem);
   H *Xp = reinterpret_cast<H *>(smem);
   H *Ea = Xp + 2 * kPlane;
   H *Eb = Ea + 2 * kPlane;
-
   const int t = threadIdx.x;
   const int lane = t & 63, w = t >> 6;
   const int g = lane >> 4, c = lane & 15, h = g & 1;
-  const int sb = blockIdx.x % nsb;
-  const int zg = blockIdx.x / nsb;
-  const int s = sb;
-  const bool active = s < nseg;
   const int64_t seg0 = (int64_t)s * U - half;
-  const int z0 = zg * zpb;
-  const int z1 = min(nz, z0 + zpb);
+  const v8 &bF1 = K.bF1, &bF2 = K.bF2;
+  const auto &bT1 = K.bT1;
+  const auto &bT2 = K.bT2;
+  const auto &tw1 = K.tw1;
+  const auto &tw2 = K.tw2;
 
-  // ---- forward FFT, FP32, decimation in frequency -------------------------
+  // ---- forward FFT, FP32, decimation in frequency, threads 0..255 ---------
+  // (threads above 255 only join the barriers)
+  const bool fw = t < kT;
   c32 x[16];
 #pragma unroll
   for (int n = 0; n < 16; ++n) {
     const int64_t gi = seg0 + n * 256 + t;
     c32 v = {0.f, 0.f};
-    if (active && gi >= 0 && gi < nbins) v = spec[gi];
+    if (fw && active && gi >= 0 && gi < nbins) v = spec[gi];
     x[n] = v;
   }
-  dft<-1, 16>(x);
+  if (fw) {
+    dft<-1, 16>(x);
 #pragma unroll
-  for (int k = 1; k < 16; ++k) x[k] = cmul(x[k], tw[k * t]);  // W_4096^(k m), m = t
+    for (int k = 1; k < 16; ++k) x[k] = cmul(x[k], tw[k * t]);  // W_4096^(k m), m = t < 256
 #pragma unroll
-  for (int n = 0; n < 16; ++n) fbuf[fpad(fwd_addr<0>(t, n))] = x[n];
+    for (int n = 0; n < 16; ++n) fbuf[fpad(fwd_addr<0>(t, n))] = x[n];
+  }
   __syncthreads();
+  if (fw) {
 #pragma unroll
-  for (int n = 0; n < 16; ++n) x[n] = fbuf[fpad(fwd_addr<1>(t, n))];
-  dft<-1, 16>(x);
-  {
+    for (int n = 0; n < 16; ++n) x[n] = fbuf[fpad(fwd_addr<1>(t, n))];
+    dft<-1, 16>(x);
     const int mi = t % 16;
 #pragma unroll
     for (int k = 1; k < 16; ++k) x[k] = cmul(x[k], tw[(k * mi) * 16]);  // W_256^(k m)
   }
   __syncthreads();
+  if (fw) {
 #pragma unroll
-  for (int n = 0; n < 16; ++n) fbuf[fpad(fwd_addr<1>(t, n))] = x[n];
+    for (int n = 0; n < 16; ++n) fbuf[fpad(fwd_addr<1>(t, n))] = x[n];
+  }
   __syncthreads();
+  if (fw) {
 #pragma unroll
-  for (int n = 0; n < 16; ++n) x[n] = fbuf[fpad(fwd_addr<2>(t, n))];
-  dft<-1, 16>(x);
+    for (int n = 0; n < 16; ++n) x[n] = fbuf[fpad(fwd_addr<2>(t, n))];
+    dft<-1, 16>(x);
+  }
   // thread t now holds X[k0 + 16 k1 + 256 e] with t = 16 k0 + k1
 
   // per-segment scale: largest component into [4, 8)
@@ -191,7 +214,9 @@ __global__ void __launch_bounds__(256)
   for (int off = 32; off >= 1; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
   if (lane == 0) s_max[w] = mx;
   __syncthreads();  // also: every forward read of fbuf is complete
-  mx = fmaxf(fmaxf(s_max[0], s_max[1]), fmaxf(s_max[2], s_max[3]));
+  mx = 0.f;
+#pragma unroll
+  for (int k = 0; k < NW; ++k) mx = fmaxf(mx, s_max[k]);
   int ex = 0;
   if (mx > 0.f) (void)frexpf(mx, &ex);
   const float xscale = ldexpf(1.0f, 3 - ex);
@@ -199,60 +224,45 @@ __global__ void __launch_bounds__(256)
   const float pscale = ldexpf(1.0f, -2 * (3 - ex + bank_log2));
 #pragma unroll
   for (int e0 = 0; e0 < 16; e0 += 4) {
+    if (!fw) break;
     store4<H>(Xp, t, e0, x[e0].x * xscale, x[e0 + 1].x * xscale, x[e0 + 2].x * xscale,
               x[e0 + 3].x * xscale);
     store4<H>(Xp + kPlane, t, e0, x[e0].y * xscale, x[e0 + 1].y * xscale, x[e0 + 2].y * xscale,
               x[e0 + 3].y * xscale);
   }
 
-  // ---- per-lane constants ----------------------------------------------------
-  v8 bF1, bF2;  // plain inverse DFT16 (phase 0)
-  make_b<H>(lane, 0, bF1, bF2);
-  v8 bT1[4], bT2[4];  // stage 0' tiles n1 = 4w + j: factor w256^(n1 k0) folded in
-#pragma unroll
-  for (int j = 0; j < 4; ++j) make_b<H>(lane, 4 * w + j, bT1[j], bT2[j]);
-  c32 tw1[4];     // after stage 2': w256^(k1 n2), k1 = 4g + i, n2 = c
-  c32 tw2[4][4];  // after stage 1': w4096^(k0 n2), k0 = 4g + i, n2 = 4w + j
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    tw1[i] = wpos(((4 * g + i) * c) & 255, 256);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) tw2[j][i] = wpos(((4 * g + i) * (4 * w + j)) & 4095, 4096);
-  }
   __syncthreads();  // X complete
 
   const H *Xre = Xp, *Xim = Xp + kPlane;
   // bank rows are read one template ahead (tiles k0 = 4w + j, rows 16 k0 + c, chunk h)
-  v8 btr[4], bti[4];
+  // re lanes compute xr*tr + xi*(-ti), im lanes xr*ti + xi*tr: plane offsets
+  const int pu = (g < 2 ? 0 : 1) * L, pv = (g < 2 ? 2 : 0) * L;
+  v8 btr[TPW], bti[TPW];
   auto load_bank = [&](int iz) {
-    const H *brow = bank + (int64_t)iz * (2 * L);
+    const H *brow = bank + (int64_t)iz * (3 * L);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int row = 16 * (4 * w + j) + c;
-      btr[j] = *reinterpret_cast<const v8 *>(brow + row * 16 + 8 * h);
-      bti[j] = *reinterpret_cast<const v8 *>(brow + L + row * 16 + 8 * h);
+    for (int j = 0; j < TPW; ++j) {
+      const int row = 16 * (TPW * w + j) + c;
+      btr[j] = *reinterpret_cast<const v8 *>(brow + pu + row * 16 + 8 * h);
+      bti[j] = *reinterpret_cast<const v8 *>(brow + pv + row * 16 + 8 * h);
     }
   };
   if (PF && z0 < z1) load_bank(z0);
-  const bool re_lane = g < 2;
   for (int iz = z0; iz < z1; ++iz) {
     if (!PF) load_bank(iz);
-    // ---- product + stage 2' (tiles k0 = 4w + j; rows k1 = c; chunk h) ----
-    v8 av[4];
+    // ---- product + stage 2' (tiles k0 = TPW w + j; rows k1 = c; chunk h) ----
+    v8 av[TPW];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int row = 16 * (4 * w + j) + c;
+    for (int j = 0; j < TPW; ++j) {
+      const int row = 16 * (TPW * w + j) + c;
       const v8 xr = load8<H>(Xre, row, 8 * h);
       const v8 xi = load8<H>(Xim, row, 8 * h);
-      // re lanes: xr*tr - xi*ti ; im lanes: xr*ti + xi*tr
-      const v8 u = re_lane ? btr[j] : bti[j];
-      const v8 v = re_lane ? -bti[j] : btr[j];
-      av[j] = xr * u + xi * v;
+      av[j] = xr * btr[j] + xi * bti[j];
     }
     if (PF && iz + 1 < z1) load_bank(iz + 1);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int k0 = 4 * w + j;
+    for (int j = 0; j < TPW; ++j) {
+      const int k0 = TPW * w + j;
       f4 zero = {0.f, 0.f, 0.f, 0.f};
       const f4 dr = Vec<H>::mfma(av[j], bF1, zero);
       const f4 di = Vec<H>::mfma(av[j], bF2, zero);
@@ -269,10 +279,10 @@ __global__ void __launch_bounds__(256)
       store4<H>(Ea + kPlane, orow, 4 * g, oii[0], oii[1], oii[2], oii[3]);
     }
     __syncthreads();
-    // ---- stage 1' (tiles n2 = 4w + j; rows k0 = c) ---------------------------
+    // ---- stage 1' (tiles n2 = TPW w + j; rows k0 = c) -------------------------
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int n2 = 4 * w + j;
+    for (int j = 0; j < TPW; ++j) {
+      const int n2 = TPW * w + j;
       const int row = 16 * n2 + c;
       const v8 a = load8<H>(Ea + (g >> 1) * kPlane, row, 8 * h);
       f4 zero = {0.f, 0.f, 0.f, 0.f};
@@ -291,11 +301,11 @@ __global__ void __launch_bounds__(256)
       store4<H>(Eb + kPlane, orow, 4 * g, oii[0], oii[1], oii[2], oii[3]);
     }
     __syncthreads();
-    // ---- stage 0' (tiles n1 = 4w + j; rows n2 = c) + |.|^2 --------------------
-    float *prow = power + (int64_t)iz * ld;
+    // ---- stage 0' (tiles n1 = TPW w + j; rows n2 = c) + |.|^2 -----------------
+    float *prow = power + (int64_t)(iz - row_base) * ld;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int n1 = 4 * w + j;
+    for (int j = 0; j < TPW; ++j) {
+      const int n1 = TPW * w + j;
       const int row = 16 * n1 + c;
       const v8 a = load8<H>(Eb + (g >> 1) * kPlane, row, 8 * h);
       f4 zero = {0.f, 0.f, 0.f, 0.f};
@@ -309,7 +319,7 @@ __global__ void __launch_bounds__(256)
         f4 pw;
 #pragma unroll
         for (int i = 0; i < 4; ++i) pw[i] = (dr[i] * dr[i] + di[i] * di[i]) * pscale;
-        if (o0 >= half && o0 + 3 < half + U && r0 + 3 < nbins && ((r0 + iz * ld) & 3) == 0) {
+        if (o0 >= half && o0 + 3 < half + U && r0 + 3 < nbins && ((reinterpret_cast<uintptr_t>(prow + r0) & 15) == 0)) {
           if constexpr (NT) __builtin_nontemporal_store(pw, reinterpret_cast<f4 *>(prow + r0));
           else *reinterpret_cast<f4 *>(prow + r0) = pw;
         } else {
@@ -324,24 +334,92 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-template <class H, bool PF, bool NT>
+template <class H, bool PF, bool NT, int NW>
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW == 8 ? 4 : 2)))
+    ols_mixed4096_kernel(const c32 *__restrict__ spec, int64_t nbins, const H *__restrict__ bank,
+                         const c32 *__restrict__ tw, const unsigned char *__restrict__ consts,
+                         float *__restrict__ power, int64_t ld, int nseg, int U, int half, int nz,
+                         int zpb, int nsb, int bank_log2) {
+  __shared__ __attribute__((aligned(16))) unsigned char smem[kMixSmem];
+  __shared__ float s_max[NW];
+  const int t = threadIdx.x;
+  MixedConsts<H, NW> K;
+  load_mixed_consts<H, NW>(K, consts, t & 63, t >> 6);
+  const int sb = blockIdx.x % nsb;
+  const int zg = blockIdx.x / nsb;
+  const int z0 = zg * zpb;
+  const int z1 = min(nz, z0 + zpb);
+  mixed_unit<H, PF, NT, NW>(K, spec, nbins, bank, tw, power, ld, sb, sb < nseg, U, half, z0, z1,
+                            0, bank_log2, smem, s_max);
+}
+
+// Batched form as one flat launch: block b takes work item b (items are
+// numbered largest series first, template-group major), so the hardware
+// dispatcher hands out items in that order as blocks retire. Same body as
+// the single-series kernel; used because the persistent loop around this
+// body does not fit the register budget.
+template <class H, bool PF, bool NT, int NW>
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW == 8 ? 4 : 2)))
+    ols_mixed4096_items_kernel(const SeriesDesc *__restrict__ desc, int nseries,
+                               const H *__restrict__ bank, const c32 *__restrict__ tw,
+                               const unsigned char *__restrict__ consts, int U, int half, int zpb,
+                               int bank_log2) {
+  __shared__ __attribute__((aligned(16))) unsigned char smem[kMixSmem];
+  __shared__ float s_max[NW];
+  const int t = threadIdx.x;
+  const long long item = blockIdx.x;
+  int lo = 0, hi = nseries - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (desc[mid].item_begin <= item) lo = mid;
+    else hi = mid - 1;
+  }
+  const SeriesDesc d = desc[lo];
+  const long long local = item - d.item_begin;
+  const int zg = (int)(local / d.nseg);
+  const int sb = (int)(local % d.nseg);
+  const int z0 = d.row_off + zg * zpb;
+  const int z1 = min(d.row_off + d.nz, z0 + zpb);
+  MixedConsts<H, NW> K;
+  load_mixed_consts<H, NW>(K, consts, t & 63, t >> 6);
+  mixed_unit<H, PF, NT, NW>(K, static_cast<const c32 *>(d.spec), d.nbins, bank, tw, d.power,
+                            d.ld, sb, true, U, half, z0, z1, d.row_off, bank_log2, smem, s_max);
+}
+
+template <class H, bool PF, bool NT, int NW>
 static hipError_t launch_mixed4096(const OlsArgs &a, hipStream_t st) {
   const int nsb = a.nseg;
   const int nzg = (a.nz + a.zpb - 1) / a.zpb;
   const long blocks = (long)nsb * nzg;
-  hipLaunchKernelGGL((ols_mixed4096_kernel<H, PF, NT>), dim3((unsigned)blocks), dim3(256), 0, st,
+  hipLaunchKernelGGL((ols_mixed4096_kernel<H, PF, NT, NW>), dim3((unsigned)blocks), dim3(64 * NW), 0, st,
                      static_cast<const c32 *>(a.spec), a.nbins, static_cast<const H *>(a.bank),
-                     static_cast<const c32 *>(a.tw), a.power, a.ld, a.nseg, a.U, a.half, a.nz,
-                     a.zpb, nsb, a.bank_log2);
+                     static_cast<const c32 *>(a.tw),
+                     static_cast<const unsigned char *>(a.consts), a.power, a.ld, a.nseg, a.U,
+                     a.half, a.nz, a.zpb, nsb, a.bank_log2);
   return hipGetLastError();
 }
 
-template <class H, bool PF = false, bool NT = true>
+template <class H, bool PF, bool NT, int NW>
+static hipError_t launch_mixed4096_batch(const BatchArgs &a, hipStream_t st) {
+  if (a.total > (int64_t)0xffffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((ols_mixed4096_items_kernel<H, PF, NT, NW>), dim3((unsigned)a.total),
+                     dim3(64 * NW), 0, st, a.desc, a.nseries, static_cast<const H *>(a.bank),
+                     static_cast<const c32 *>(a.tw), static_cast<const unsigned char *>(a.consts),
+                     a.U, a.half, a.zpb, a.bank_log2);
+  return hipGetLastError();
+}
+
+template <class H, bool PF, bool NT, int NW>
+static int mixed_batch_blocks_per_cu() {
+  return 1;  // flat launch: the grid is the item count
+}
+
+template <class H, bool PF = false, bool NT = true, int NW = 8>
 static OlsVariant make_mixed(const char *name, int precision) {
   OlsVariant v{};
   v.name = name;
   v.L = 4096;
-  v.T = 256;
+  v.T = 64 * NW;
   v.G = 1;
   v.nbuf = 1;
   v.precision = precision;
@@ -352,17 +430,18 @@ static OlsVariant make_mixed(const char *name, int precision) {
   v.lay.R[0] = v.lay.R[1] = v.lay.R[2] = 16;
   for (int i = 3; i < kMaxStages; ++i) v.lay.R[i] = 1;
   v.lds_bytes = 0;
-  v.launch = &launch_mixed4096<H, PF, NT>;
-  v.launch_batch = nullptr;
-  v.batch_blocks_per_cu = nullptr;
+  v.launch = &launch_mixed4096<H, PF, NT, NW>;
+  v.launch_batch = &launch_mixed4096_batch<H, PF, NT, NW>;
+  v.batch_blocks_per_cu = &mixed_batch_blocks_per_cu<H, PF, NT, NW>;
   return v;
 }
 
 static const OlsVariant kMixedVariants[] = {
-    make_mixed<_Float16>("fp16_L4096_mfma_r16.16.16", 1),
-    make_mixed<_Float16, true, true>("fp16_L4096_mfma_r16.16.16_pf", 1),
-    make_mixed<_Float16, false, false>("fp16_L4096_mfma_r16.16.16_ts", 1),
-    make_mixed<__bf16>("bf16_L4096_mfma_r16.16.16", 2),
+    make_mixed<_Float16>("fp16_L4096_mfma_w8", 1),
+    make_mixed<_Float16, false, true, 4>("fp16_L4096_mfma_w4", 1),
+    make_mixed<_Float16, true, true>("fp16_L4096_mfma_w8_pf", 1),
+    make_mixed<_Float16, false, false>("fp16_L4096_mfma_w8_ts", 1),
+    make_mixed<__bf16>("bf16_L4096_mfma_w8", 2),
 };
 
 const OlsVariant *mixed_variants(int *count) {
@@ -399,9 +478,10 @@ __global__ void bank_mixed_kernel(H *__restrict__ bank, const c64m *__restrict__
     sr += v.x * cs - v.y * sn;
     si += v.x * sn + v.y * cs;
   }
-  H *row_i = bank + (long)i * 2 * L;
-  row_i[slot] = (H)sr;
-  row_i[L + slot] = (H)(-si);
+  H *row_i = bank + (long)i * 3 * L;
+  row_i[slot] = (H)sr;             // Re T'
+  row_i[L + slot] = (H)(-si);      // Im T'
+  row_i[2 * L + slot] = (H)si;     // -Im T'
 }
 
 template <class H>
@@ -413,9 +493,57 @@ __global__ void bank_mixed_natural_kernel(c32 *__restrict__ dst, const H *__rest
   const int slot = (int)(idx % L);
   const int row = slot >> 4, k2 = slot & 15;
   const int k = (row >> 4) + 16 * (row & 15) + 256 * k2;
-  const H *row_i = bank + (long)i * 2 * L;
+  const H *row_i = bank + (long)i * 3 * L;
   const float inv = 1.0f / (float)L;
   dst[(long)i * L + k] = {(float)row_i[slot] * inv, (float)row_i[L + slot] * inv};
+}
+
+// Per-lane constants of the mixed kernel, generated in FP64.
+template <class H>
+__global__ void mixed_consts_kernel(unsigned char *__restrict__ out) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const double kTwoPi = 6.283185307179586476925;
+  if (idx < 17 * 64) {
+    const int mat = idx / 64, lane = idx % 64;
+    const int phase = mat == 0 ? 0 : mat - 1;
+    const int c = lane & 15, kg = lane >> 4;
+    H *b = reinterpret_cast<H *>(out) + (size_t)idx * 16;
+    for (int j = 0; j < 8; ++j) {
+      const int kk = kg * 8 + j, k = kk & 15;
+      double sn, cs;
+      sincos(kTwoPi * (double)((k * (16 * c + phase)) & 255) / 256.0, &sn, &cs);
+      b[j] = (H)(kk < 16 ? cs : -sn);      // B1 = [Re M | -Im M]
+      b[8 + j] = (H)(kk < 16 ? sn : cs);   // B2 = [Im M | Re M]
+    }
+  }
+  c32 *tw = reinterpret_cast<c32 *>(out + kConstB);
+  if (idx < 64 * 4) {
+    const int lane = idx / 4, i = idx % 4;
+    const int g = lane >> 4, c = lane & 15;
+    double sn, cs;
+    sincos(kTwoPi * (double)(((4 * g + i) * c) & 255) / 256.0, &sn, &cs);
+    tw[idx] = {(float)cs, (float)sn};
+  }
+  if (idx < 16 * 64 * 4) {
+    const int tile = idx / 256, lane = (idx / 4) % 64, i = idx % 4;
+    const int g = lane >> 4;
+    double sn, cs;
+    sincos(kTwoPi * (double)(((4 * g + i) * tile) & 4095) / 4096.0, &sn, &cs);
+    tw[256 + idx] = {(float)cs, (float)sn};
+  }
+}
+
+size_t mixed_consts_bytes(int L) { return L == 4096 ? (size_t)kConstBytes : 0; }
+
+hipError_t launch_mixed_consts(void *out, int L, int precision, hipStream_t s) {
+  if (L != 4096) return hipErrorInvalidValue;
+  if (precision == 2)
+    hipLaunchKernelGGL(mixed_consts_kernel<__bf16>, dim3(16), dim3(256), 0, s,
+                       static_cast<unsigned char *>(out));
+  else
+    hipLaunchKernelGGL(mixed_consts_kernel<_Float16>, dim3(16), dim3(256), 0, s,
+                       static_cast<unsigned char *>(out));
+  return hipGetLastError();
 }
 
 hipError_t launch_bank_mixed(void *bank, const void *h, int nz, int m, int L, int precision,

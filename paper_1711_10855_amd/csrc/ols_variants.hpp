@@ -23,6 +23,7 @@ struct OlsArgs {
   int nz;            // rows to produce
   int zpb;           // templates per work unit
   int bank_log2;     // mixed precision: the bank is stored times 2^bank_log2
+  const void *consts;  // mixed precision: per-lane constants table
 };
 
 // One series of a batch as the persistent kernel sees it.
@@ -47,6 +48,8 @@ struct BatchArgs {
   const void *tw;
   int U, half, zpb;
   int grid;             // persistent blocks
+  int bank_log2;        // mixed precision: bank scale
+  const void *consts;   // mixed precision: per-lane constants
 };
 
 struct OlsVariant {
@@ -64,6 +67,8 @@ const OlsVariant *fp32_variants(int *count);
 const OlsVariant *mixed_variants(int *count);
 hipError_t launch_bank_mixed(void *bank, const void *h, int nz, int m, int L, int precision,
                              hipStream_t s);
+size_t mixed_consts_bytes(int L);
+hipError_t launch_mixed_consts(void *out, int L, int precision, hipStream_t s);
 hipError_t launch_bank_mixed_natural(c32 *dst, const void *bank, int nz, int L, int precision,
                                      hipStream_t s);
 

@@ -23,16 +23,23 @@ struct fdas_plan_s {
   void *bank = nullptr;
   size_t bank_bytes = 0;
   void *tw = nullptr;
+  void *consts = nullptr;
   double plan_ms = 0.0;
-  // batched path
+  // batched path: one captured graph (and descriptor table) per batch layout
+  struct GraphEntry {
+    std::vector<fdas::SeriesDesc> key;
+    fdas::SeriesDesc *d_desc = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t last_use = 0;
+  };
   unsigned long long *counter = nullptr;
-  fdas::SeriesDesc *d_desc = nullptr;
-  size_t desc_cap = 0;
-  std::vector<fdas::SeriesDesc> last_desc;
+  std::vector<GraphEntry> graphs;
+  uint64_t use_clock = 0;
   hipStream_t cap_stream = nullptr;
-  hipGraphExec_t graph = nullptr;
   int cus = 0;
 };
+
+static constexpr size_t kMaxGraphs = 8;
 
 namespace fdas {
 
@@ -62,10 +69,186 @@ static int default_zpb(int nz) {
   return (nz + groups - 1) / groups;
 }
 
+static int build_plan_with(fdas_plan_t *out, const fdas_params &p, int nz, int device,
+                           hipStream_t s, const OlsVariant *force_var, int force_zpb);
+
+// Autotuner: time every compiled variant for every admissible segment length
+// (U = L - m >= L/2 unless the caller fixed L) and a few template-group sizes
+// on a synthetic spectrum, keep the fastest per plane point. Results are
+// cached in a text file (FDAS_TUNE_CACHE, one line per key) keyed by device
+// architecture, CU count, m, nz and precision.
+struct TuneChoice {
+  const OlsVariant *var = nullptr;
+  int L = 0, zpb = 0;
+  double ns_per_point = 0.0;
+};
+
+static std::string tune_key(const fdas_params &p, int nz, int device) {
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  int cus = 0;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+    arch = prop.gcnArchName;
+    cus = prop.multiProcessorCount;
+  }
+  for (auto &ch : arch)
+    if (ch == ' ' || ch == ':') ch = '_';
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), "%s cu%d m%d nz%d prec%d L%d", arch.c_str(), cus, p.m, nz,
+                p.precision, p.seg_len);
+  return buf;
+}
+
+static const OlsVariant *variant_by_name(const char *name) {
+  for (int pass = 0; pass < 2; ++pass) {
+    int n = 0;
+    const OlsVariant *v = pass == 0 ? fp32_variants(&n) : mixed_variants(&n);
+    for (int i = 0; i < n; ++i)
+      if (std::strcmp(v[i].name, name) == 0) return &v[i];
+  }
+  return nullptr;
+}
+
+static bool tune_cache_lookup(const std::string &key, TuneChoice *c) {
+  const char *path = std::getenv("FDAS_TUNE_CACHE");
+  if (!path || !*path) return false;
+  FILE *f = std::fopen(path, "r");
+  if (!f) return false;
+  char line[512];
+  bool found = false;
+  while (std::fgets(line, sizeof(line), f)) {
+    std::string ln(line);
+    const size_t bar = ln.find(" | ");
+    if (bar == std::string::npos || ln.compare(0, bar, key) != 0) continue;
+    char name[128];
+    int L = 0, zpb = 0;
+    double ns = 0;
+    if (std::sscanf(ln.c_str() + bar + 3, "%127s %d %d %lf", name, &L, &zpb, &ns) == 4) {
+      const OlsVariant *v = variant_by_name(name);
+      if (v && v->L == L) {
+        c->var = v;
+        c->L = L;
+        c->zpb = zpb;
+        c->ns_per_point = ns;
+        found = true;
+      }
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+static void tune_cache_store(const std::string &key, const TuneChoice &c) {
+  const char *path = std::getenv("FDAS_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE *f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%s | %s %d %d %.6f\n", key.c_str(), c.var->name, c.L, c.zpb, c.ns_per_point);
+  std::fclose(f);
+}
+
+__global__ void tune_fill_kernel(c32 *spec, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) spec[i] = {1.0f + 1e-3f * (float)(i & 1023), 0.5f - 1e-3f * (float)(i & 511)};
+}
+
+static int autotune(const fdas_params &p, int nz, int device, hipStream_t s, TuneChoice *best) {
+  const int64_t nbins = (int64_t)1 << 20;
+  void *spec = nullptr;
+  float *power = nullptr;
+  hipError_t e = hipMalloc(&spec, nbins * 8);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&power), (size_t)nz * nbins * 4);
+  if (e != hipSuccess) {
+    if (spec) (void)hipFree(spec);
+    return set_error(FDAS_ERR_NOMEM, "autotune buffers: %s", hipGetErrorString(e));
+  }
+  hipLaunchKernelGGL(tune_fill_kernel, dim3((unsigned)((nbins + 255) / 256)), dim3(256), 0, s,
+                     static_cast<c32 *>(spec), nbins);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  int status = FDAS_OK;
+  best->var = nullptr;
+  for (int pass = 0; pass < 2 && status == FDAS_OK; ++pass) {
+    int n = 0;
+    const OlsVariant *vs = pass == 0 ? fp32_variants(&n) : mixed_variants(&n);
+    for (int i = 0; i < n && status == FDAS_OK; ++i) {
+      const OlsVariant *v = &vs[i];
+      if (v->precision != p.precision) continue;
+      if (p.seg_len ? v->L != p.seg_len : (v->L - p.m) * 2 < v->L) continue;
+      int last_zpb = -1;
+      for (int ng : {1, 2, 3, 4, 6, 8, 12}) {
+        const int zpb = (nz + ng - 1) / ng;
+        if (zpb == last_zpb) continue;
+        last_zpb = zpb;
+        fdas_params q = p;
+        q.seg_len = v->L;
+        fdas_plan_t pl = nullptr;
+        int st = build_plan_with(&pl, q, nz, device, s, v, zpb);
+        if (st != FDAS_OK) {
+          status = st;
+          break;
+        }
+        st = plan_convolve(pl, spec, nbins, power, nbins, s);  // warm-up
+        if (st == FDAS_OK) (void)hipEventRecord(e0, s);
+        for (int r = 0; r < 3 && st == FDAS_OK; ++r) st = plan_convolve(pl, spec, nbins, power, nbins, s);
+        float ms = 0.f;
+        if (st == FDAS_OK) {
+          (void)hipEventRecord(e1, s);
+          e = hipEventSynchronize(e1);
+          if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+          if (e != hipSuccess) st = hip_error(e, "autotune timing");
+        }
+        destroy_plan(pl);
+        if (st != FDAS_OK) {
+          status = st;
+          break;
+        }
+        const double ns = (double)ms * 1e6 / 3.0 / ((double)nz * (double)nbins);
+        if (!best->var || ns < best->ns_per_point) {
+          best->var = v;
+          best->L = v->L;
+          best->zpb = zpb;
+          best->ns_per_point = ns;
+        }
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(spec);
+  (void)hipFree(power);
+  if (status == FDAS_OK && !best->var)
+    status = set_error(FDAS_ERR_UNSUPPORTED, "no compiled variant admits m=%d", p.m);
+  return status;
+}
+
 int build_plan(fdas_plan_t *out, const fdas_params &p, int nz, int device, hipStream_t s) {
+  if (p.flags & FDAS_FLAG_AUTOTUNE) {
+    const auto t0 = std::chrono::steady_clock::now();
+    fdas_params q = p;
+    const std::string key = tune_key(p, nz, device);
+    TuneChoice c;
+    if (!tune_cache_lookup(key, &c)) {
+      int st = autotune(p, nz, device, s, &c);
+      if (st != FDAS_OK) return st;
+      tune_cache_store(key, c);
+    }
+    q.seg_len = c.L;
+    int st = build_plan_with(out, q, nz, device, s, c.var, c.zpb);
+    if (st == FDAS_OK)
+      (*out)->plan_ms =
+          std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return st;
+  }
+  return build_plan_with(out, p, nz, device, s, nullptr, 0);
+}
+
+static int build_plan_with(fdas_plan_t *out, const fdas_params &p, int nz, int device,
+                           hipStream_t s, const OlsVariant *force_var, int force_zpb) {
   const auto t0 = std::chrono::steady_clock::now();
   const char *want = std::getenv("FDAS_VARIANT");
-  const OlsVariant *var = find_variant(p.seg_len, p.precision, want);
+  const OlsVariant *var = force_var ? force_var : find_variant(p.seg_len, p.precision, want);
   if (!var) {
     if (want && *want)
       return set_error(FDAS_ERR_UNSUPPORTED, "variant '%s' not compiled for seg_len %d", want, p.seg_len);
@@ -85,13 +268,16 @@ int build_plan(fdas_plan_t *out, const fdas_params &p, int nz, int device, hipSt
     const int v = std::atoi(z);
     if (v > 0) pl->zpb = v;
   }
+  if (force_zpb > 0) pl->zpb = force_zpb;
 
   void *h = nullptr;
   const size_t hbytes = (size_t)nz * (p.m + 1) * 16;
-  pl->bank_bytes = (size_t)nz * p.seg_len * (p.precision == FDAS_FP32 ? 8 : 4);
+  pl->bank_bytes = (size_t)nz * p.seg_len * (p.precision == FDAS_FP32 ? 8 : 6);
   hipError_t e = hipMalloc(&h, hbytes);
   if (e == hipSuccess) e = hipMalloc(&pl->bank, pl->bank_bytes);
   if (e == hipSuccess) e = hipMalloc(&pl->tw, (size_t)p.seg_len * 8);
+  if (e == hipSuccess && p.precision != FDAS_FP32)
+    e = hipMalloc(&pl->consts, mixed_consts_bytes(p.seg_len));
   if (e != hipSuccess) {
     if (h) (void)hipFree(h);
     destroy_plan(pl);
@@ -111,6 +297,7 @@ int build_plan(fdas_plan_t *out, const fdas_params &p, int nz, int device, hipSt
       e = launch_bank_mixed(pl->bank, h, nz, p.m, p.seg_len, p.precision, s);
   }
   if (e == hipSuccess) e = launch_twiddles(static_cast<c32 *>(pl->tw), p.seg_len, s);
+  if (e == hipSuccess && pl->consts) e = launch_mixed_consts(pl->consts, p.seg_len, p.precision, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   (void)hipFree(h);
   if (e != hipSuccess) {
@@ -196,6 +383,7 @@ int plan_convolve(fdas_plan_t pl, const void *spec, int64_t nbins, float *power,
   a.zpb = pl->zpb;
   a.bank_log2 = 0;
   while ((1 << a.bank_log2) < pl->L) ++a.bank_log2;
+  a.consts = pl->consts;
   hipError_t e = pl->var->launch(a, s);
   if (e != hipSuccess) return hip_error(e, "correlation kernel launch");
   return FDAS_OK;
@@ -246,38 +434,54 @@ int plan_convolve_batch(fdas_plan_t pl, const fdas_series *series, int nseries, 
   }
   if (total == 0) return FDAS_OK;
 
-  const bool same = pl->graph && sorted.size() == pl->last_desc.size() &&
-                    std::memcmp(sorted.data(), pl->last_desc.data(), sorted.size() * sizeof(SeriesDesc)) == 0;
   hipError_t e = hipSuccess;
-  if (!same) {
-    // new batch layout: upload descriptors and capture a fresh graph
+  auto &graphs = pl->graphs;
+  fdas_plan_s::GraphEntry *hit = nullptr;
+  for (auto &ge : graphs)
+    if (ge.key.size() == sorted.size() &&
+        std::memcmp(ge.key.data(), sorted.data(), sorted.size() * sizeof(SeriesDesc)) == 0) {
+      hit = &ge;
+      break;
+    }
+  const char *nog = std::getenv("FDAS_NO_GRAPH");
+  const bool eager = nog && *nog == '1';
+  if (!hit || eager) {
+    // new batch layout: upload its descriptors and capture a graph for it
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_error(e, "synchronise before descriptor upload");
-    if (pl->graph) {
-      (void)hipGraphExecDestroy(pl->graph);
-      pl->graph = nullptr;
+    if (!hit && graphs.size() >= kMaxGraphs) {  // evict the least recently used layout
+      size_t old = 0;
+      for (size_t i = 1; i < graphs.size(); ++i)
+        if (graphs[i].last_use < graphs[old].last_use) old = i;
+      if (graphs[old].exec) (void)hipGraphExecDestroy(graphs[old].exec);
+      if (graphs[old].d_desc) (void)hipFree(graphs[old].d_desc);
+      graphs.erase(graphs.begin() + old);
     }
-    if (pl->desc_cap < sorted.size()) {
-      if (pl->d_desc) (void)hipFree(pl->d_desc);
-      pl->d_desc = nullptr;
-      pl->desc_cap = 0;
-      e = hipMalloc(&pl->d_desc, sorted.size() * sizeof(SeriesDesc));
-      if (e != hipSuccess) return set_error(FDAS_ERR_NOMEM, "descriptor allocation: %s", hipGetErrorString(e));
-      pl->desc_cap = sorted.size();
+    fdas_plan_s::GraphEntry ent;
+    e = hipMalloc(&ent.d_desc, sorted.size() * sizeof(SeriesDesc));
+    if (e != hipSuccess) return set_error(FDAS_ERR_NOMEM, "descriptor allocation: %s", hipGetErrorString(e));
+    e = hipMemcpy(ent.d_desc, sorted.data(), sorted.size() * sizeof(SeriesDesc), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(ent.d_desc);
+      return hip_error(e, "descriptor upload");
     }
-    e = hipMemcpy(pl->d_desc, sorted.data(), sorted.size() * sizeof(SeriesDesc), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_error(e, "descriptor upload");
     if (!pl->cap_stream) {
       e = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking);
-      if (e != hipSuccess) return hip_error(e, "capture stream");
+      if (e != hipSuccess) {
+        (void)hipFree(ent.d_desc);
+        return hip_error(e, "capture stream");
+      }
     }
     if (!pl->cus) {
       e = hipDeviceGetAttribute(&pl->cus, hipDeviceAttributeMultiprocessorCount, pl->device);
-      if (e != hipSuccess) return hip_error(e, "CU count");
+      if (e != hipSuccess) {
+        (void)hipFree(ent.d_desc);
+        return hip_error(e, "CU count");
+      }
     }
     const int per_cu = std::max(1, pl->var->batch_blocks_per_cu());
     BatchArgs a;
-    a.desc = pl->d_desc;
+    a.desc = ent.d_desc;
     a.nseries = nseries;
     a.total = total;
     a.counter = pl->counter;
@@ -287,31 +491,42 @@ int plan_convolve_batch(fdas_plan_t pl, const fdas_series *series, int nseries, 
     a.half = pl->m / 2;
     a.zpb = pl->zpb;
     a.grid = (int)std::min<int64_t>((int64_t)pl->cus * per_cu, total);
-    const char *nog = std::getenv("FDAS_NO_GRAPH");
-    if (nog && *nog == '1') {
+    a.bank_log2 = 0;
+    while ((1 << a.bank_log2) < pl->L) ++a.bank_log2;
+    a.consts = pl->consts;
+    if (eager) {
       e = pl->var->launch_batch(a, s);
+      hipError_t e2 = hipStreamSynchronize(s);
+      (void)hipFree(ent.d_desc);
       if (e != hipSuccess) return hip_error(e, "batch kernel launch");
-      return FDAS_OK;  // nothing cached: the next call uploads again
+      if (e2 != hipSuccess) return hip_error(e2, "batch kernel");
+      return FDAS_OK;
     }
     hipGraph_t g = nullptr;
     e = hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) return hip_error(e, "begin capture");
+    if (e != hipSuccess) {
+      (void)hipFree(ent.d_desc);
+      return hip_error(e, "begin capture");
+    }
     hipError_t le = pl->var->launch_batch(a, pl->cap_stream);
     e = hipStreamEndCapture(pl->cap_stream, &g);
-    if (le != hipSuccess) {
+    if (le != hipSuccess || e != hipSuccess) {
       if (g) (void)hipGraphDestroy(g);
-      return hip_error(le, "batch kernel capture");
+      (void)hipFree(ent.d_desc);
+      return hip_error(le != hipSuccess ? le : e, "batch kernel capture");
     }
-    if (e != hipSuccess) return hip_error(e, "end capture");
-    e = hipGraphInstantiate(&pl->graph, g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&ent.exec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
-      pl->graph = nullptr;
+      (void)hipFree(ent.d_desc);
       return hip_error(e, "graph instantiate");
     }
-    pl->last_desc = sorted;
+    ent.key = sorted;
+    graphs.push_back(std::move(ent));
+    hit = &graphs.back();
   }
-  e = hipGraphLaunch(pl->graph, s);
+  hit->last_use = ++pl->use_clock;
+  e = hipGraphLaunch(hit->exec, s);
   if (e != hipSuccess) return hip_error(e, "graph launch");
   return FDAS_OK;
 }
@@ -319,13 +534,16 @@ int plan_convolve_batch(fdas_plan_t pl, const fdas_series *series, int nseries, 
 int destroy_plan(fdas_plan_t pl) {
   if (!pl) return FDAS_OK;
   hipError_t e = hipSuccess;
-  if (pl->bank || pl->tw || pl->counter) e = hipDeviceSynchronize();
-  if (pl->graph) (void)hipGraphExecDestroy(pl->graph);
+  if (pl->bank || pl->tw || pl->counter || pl->consts) e = hipDeviceSynchronize();
+  for (auto &ge : pl->graphs) {
+    if (ge.exec) (void)hipGraphExecDestroy(ge.exec);
+    if (ge.d_desc) (void)hipFree(ge.d_desc);
+  }
   if (pl->cap_stream) (void)hipStreamDestroy(pl->cap_stream);
-  if (pl->d_desc) (void)hipFree(pl->d_desc);
   if (pl->counter) (void)hipFree(pl->counter);
   if (pl->bank) (void)hipFree(pl->bank);
   if (pl->tw) (void)hipFree(pl->tw);
+  if (pl->consts) (void)hipFree(pl->consts);
   delete pl;
   if (e != hipSuccess) return hip_error(e, "synchronise before destroy");
   return FDAS_OK;

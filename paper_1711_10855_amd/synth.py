@@ -193,12 +193,43 @@ def batch_specs(name: str, nseries: int | None = None):
 
 
 def batch_spectrum(name: str, spec: SeriesSpec) -> np.ndarray:
-    """complex64 spectrum of one series of a batched workload (seeded by j)."""
+    """complex64 spectrum of one series of a batched workload (seeded by j).
+
+    The white-noise part is drawn directly in the Fourier domain, where the
+    real FFT of N(0,1) samples is exactly i.i.d. complex Gaussian with
+    E|A_k|^2 = N for 0 < k < N/2; the chirps are synthesised in time and
+    transformed (one FFT per series that has any). DC is zeroed and the
+    spectrum is normalised by its median power as for single series.
+    """
+    import scipy.fft
+
     w = WORKLOADS[name]
     child = workload_rng(w.index).spawn(w.nseries)[spec.index]
     rng = np.random.default_rng(child)
-    x = make_series(spec.n_samples, spec.chirps, rng)
-    return make_spectrum(x).astype(np.complex64)
+    n = spec.n_samples
+    nb = n // 2
+    scale = math.sqrt(n / 2.0)
+    a = np.empty(nb, dtype=np.complex128)
+    a.real = rng.standard_normal(nb)
+    a.imag = rng.standard_normal(nb)
+    a *= scale
+    if spec.chirps:
+        x = make_series(n, spec.chirps, rng, noise=False)
+        a += scipy.fft.rfft(x, workers=1)[:nb]
+    a[0] = 0.0
+    p = a[1:].real ** 2 + a[1:].imag ** 2
+    a /= math.sqrt(float(np.median(p)) / math.log(2.0))
+    return a.astype(np.complex64)
+
+
+def batch_inputs(name: str, nseries: int | None = None, workers: int = 16):
+    """Specs and complex64 spectra of a batched workload, built in threads."""
+    import concurrent.futures as cf
+
+    specs = batch_specs(name, nseries)
+    with cf.ThreadPoolExecutor(max_workers=workers) as ex:
+        spectra = list(ex.map(lambda sp: batch_spectrum(name, sp), specs))
+    return specs, spectra
 
 
 def noise_free_chirp_spectrum(n: int, chirp: Chirp) -> np.ndarray:

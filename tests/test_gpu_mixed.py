@@ -89,3 +89,20 @@ def test_mixed_workload_sampled_points(gpu):
     err = float(np.max(np.abs(p[iz, r] - ref)) / ref.max())
     print(f"mixed-paper fp16 sampled max|dP|/maxP = {err:.3e}")
     assert err <= TOL_MIXED
+
+
+def test_mixed_batch_matches_oracle(gpu):
+    import torch
+    specs = [(9000, 16.0), (1, 4.0), (4100, 0.0), (20000, 10.0), (3841, 16.0)]
+    spectra = [synth.small_random_spectrum(n, seed=300 + k) for k, (n, _) in enumerate(specs)]
+    outs = [torch.full((int(round(z)) + 1, n + 2), -5.0, dtype=torch.float32, device="cuda")
+            for n, z in specs]
+    with gpu.Plan(16.0, 2.0, 256, 4096, "fp16") as p:
+        p.convolve_batch([to_dev(a) for a in spectra], [z for _, z in specs], outs)
+        res = [o.cpu().numpy() for o in outs]
+    for (n, z), a, o in zip(specs, spectra, res):
+        ref = oracle.plane_direct(a, z, 2.0, 256)
+        err = rel_err(o[:, :n], ref)
+        print(f"fp16 batch nbins={n} zmax={z}: {err:.3e}")
+        assert err <= TOL_MIXED
+        assert np.all(o[:, n:] == -5.0)
