@@ -141,6 +141,110 @@ __device__ __forceinline__ void dft16(c32 *v) {
   t = v[11]; v[11] = v[14]; v[14] = t;
 }
 
+// ---- twiddled butterflies ---------------------------------------------------
+// Radix-R DFT of inputs v[k] * w[k] (w[0] = 1 implied), with the twiddle
+// products folded into the first butterfly layer: a + b*w costs four fused
+// multiply-adds and a - b*w = 2a - (a + b*w) two more. CONJ selects conj(w).
+
+template <bool CONJ>
+__device__ __forceinline__ c32 cfma(c32 a, c32 b, c32 w) {  // a + b * w'
+  if constexpr (CONJ)
+    return {__builtin_fmaf(b.x, w.x, __builtin_fmaf(b.y, w.y, a.x)),
+            __builtin_fmaf(b.y, w.x, __builtin_fmaf(-b.x, w.y, a.y))};
+  else
+    return {__builtin_fmaf(b.x, w.x, __builtin_fmaf(-b.y, w.y, a.x)),
+            __builtin_fmaf(b.y, w.x, __builtin_fmaf(b.x, w.y, a.y))};
+}
+template <bool CONJ>
+__device__ __forceinline__ c32 cmul_t(c32 b, c32 w) {  // b * w'
+  return CONJ ? cmulc(b, w) : cmul(b, w);
+}
+__device__ __forceinline__ c32 twice_minus(c32 a, c32 s) {  // 2a - s
+  return {__builtin_fmaf(2.0f, a.x, -s.x), __builtin_fmaf(2.0f, a.y, -s.y)};
+}
+
+// First radix-2 layers of a radix-4 butterfly on (a, b, c, d) scaled by
+// (wa, wb, wc, wd); TA says whether a carries a twiddle.
+template <int DIR, bool CONJ, bool TA>
+__device__ __forceinline__ void dft4_tw(c32 &a, c32 &b, c32 &c, c32 &d, c32 wa, c32 wb, c32 wc,
+                                        c32 wd) {
+  const c32 a1 = TA ? cmul_t<CONJ>(a, wa) : a;
+  const c32 t0 = cfma<CONJ>(a1, c, wc);
+  const c32 t1 = twice_minus(a1, t0);
+  const c32 b1 = cmul_t<CONJ>(b, wb);
+  const c32 t2 = cfma<CONJ>(b1, d, wd);
+  const c32 t3 = rot90<DIR>(twice_minus(b1, t2));
+  a = cadd(t0, t2);
+  c = csub(t0, t2);
+  b = cadd(t1, t3);
+  d = csub(t1, t3);
+}
+
+template <int DIR, bool CONJ>
+__device__ __forceinline__ void dft16_tw(c32 *v, const c32 *w) {
+  const c32 one = {1.f, 0.f};
+  dft4_tw<DIR, CONJ, false>(v[0], v[4], v[8], v[12], one, w[4], w[8], w[12]);
+  dft4_tw<DIR, CONJ, true>(v[1], v[5], v[9], v[13], w[1], w[5], w[9], w[13]);
+  dft4_tw<DIR, CONJ, true>(v[2], v[6], v[10], v[14], w[2], w[6], w[10], w[14]);
+  dft4_tw<DIR, CONJ, true>(v[3], v[7], v[11], v[15], w[3], w[7], w[11], w[15]);
+  v[5] = tw16<DIR, 1>(v[5]);
+  v[9] = tw16<DIR, 2>(v[9]);
+  v[13] = tw16<DIR, 3>(v[13]);
+  v[6] = tw16<DIR, 2>(v[6]);
+  v[10] = tw16<DIR, 4>(v[10]);
+  v[14] = tw16<DIR, 6>(v[14]);
+  v[7] = tw16<DIR, 3>(v[7]);
+  v[11] = tw16<DIR, 6>(v[11]);
+  v[15] = tw16<DIR, 9>(v[15]);
+  dft4<DIR>(v[0], v[1], v[2], v[3]);
+  dft4<DIR>(v[4], v[5], v[6], v[7]);
+  dft4<DIR>(v[8], v[9], v[10], v[11]);
+  dft4<DIR>(v[12], v[13], v[14], v[15]);
+  c32 t;
+  t = v[1]; v[1] = v[4]; v[4] = t;
+  t = v[2]; v[2] = v[8]; v[8] = t;
+  t = v[3]; v[3] = v[12]; v[12] = t;
+  t = v[6]; v[6] = v[9]; v[9] = t;
+  t = v[7]; v[7] = v[13]; v[13] = t;
+  t = v[11]; v[11] = v[14]; v[14] = t;
+}
+
+template <int DIR, bool CONJ>
+__device__ __forceinline__ void dft8_tw(c32 *v, const c32 *w) {
+  const c32 one = {1.f, 0.f};
+  c32 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  c32 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+  dft4_tw<DIR, CONJ, false>(e0, e1, e2, e3, one, w[2], w[4], w[6]);
+  dft4_tw<DIR, CONJ, true>(o0, o1, o2, o3, w[1], w[3], w[5], w[7]);
+  o1 = tw16<DIR, 2>(o1);
+  o2 = tw16<DIR, 4>(o2);
+  o3 = tw16<DIR, 6>(o3);
+  v[0] = cadd(e0, o0);
+  v[4] = csub(e0, o0);
+  v[1] = cadd(e1, o1);
+  v[5] = csub(e1, o1);
+  v[2] = cadd(e2, o2);
+  v[6] = csub(e2, o2);
+  v[3] = cadd(e3, o3);
+  v[7] = csub(e3, o3);
+}
+
+template <int DIR, bool CONJ, int R>
+__device__ __forceinline__ void dft_tw(c32 *v, const c32 *w) {
+  static_assert(R == 2 || R == 4 || R == 8 || R == 16, "radix");
+  if constexpr (R == 2) {
+    const c32 t0 = cfma<CONJ>(v[0], v[1], w[1]);
+    v[1] = twice_minus(v[0], t0);
+    v[0] = t0;
+  } else if constexpr (R == 4) {
+    dft4_tw<DIR, CONJ, false>(v[0], v[1], v[2], v[3], c32{1.f, 0.f}, w[1], w[2], w[3]);
+  } else if constexpr (R == 8) {
+    dft8_tw<DIR, CONJ>(v, w);
+  } else {
+    dft16_tw<DIR, CONJ>(v, w);
+  }
+}
+
 // The pointer value passes through an empty asm statement, so loads through
 // it cannot be hoisted out of the loop the call sits in (keeps loop-invariant
 // table reads inside persistent loops instead of pinning them in registers).

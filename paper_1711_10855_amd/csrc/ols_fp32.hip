@@ -240,15 +240,16 @@ __device__ __forceinline__ void ols_unit(const c32 *__restrict__ spec, int64_t n
 #pragma unroll
         for (int j = 0; j < Gm::B(I); ++j) {
           const int mi = stage_suffix<Gm, I>(t, j);
+          c32 w[R];
 #pragma unroll
-          for (int k = 1; k < R; ++k) {
-            const c32 w = TWREG ? itw[Gm::TWOFF(I) + j * (R - 1) + k - 1] : tw[(k * mi) * (L / N)];
-            y[j * R + k] = cmulc(y[j * R + k], w);
-          }
+          for (int k = 1; k < R; ++k)
+            w[k] = TWREG ? itw[Gm::TWOFF(I) + j * (R - 1) + k - 1] : tw[(k * mi) * (L / N)];
+          dft_tw<+1, true, R>(&y[j * R], w);  // conj twiddles folded into the butterfly
         }
-      }
+      } else {
 #pragma unroll
-      for (int j = 0; j < Gm::B(I); ++j) dft<+1, R>(&y[j * R]);
+        for (int j = 0; j < Gm::B(I); ++j) dft<+1, R>(&y[j * R]);
+      }
     });
 
     // outputs: slot j*R0 + n holds index n * S0 + t + j T of the segment
@@ -371,6 +372,16 @@ static int batch_blocks_per_cu() {
   return nb;
 }
 
+template <class Gm, int G, bool TWREG, bool PF, int WPE>
+static int grid_blocks_per_cu() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &nb, reinterpret_cast<const void *>(&ols_fp32_kernel<Gm, G, TWREG, PF, WPE>), Gm::T * G,
+          0) != hipSuccess)
+    return 0;
+  return nb;
+}
+
 template <class Gm, int G, bool TWREG, bool PF, int WPE = 1>
 static constexpr OlsVariant make_variant(const char *name) {
   OlsVariant v{};
@@ -389,6 +400,7 @@ static constexpr OlsVariant make_variant(const char *name) {
   v.launch = &launch_variant<Gm, G, TWREG, PF, WPE>;
   v.launch_batch = &launch_batch_variant<Gm, G, TWREG, PF, WPE>;
   v.batch_blocks_per_cu = &batch_blocks_per_cu<Gm, G, TWREG, PF, WPE>;
+  v.grid_blocks_per_cu = &grid_blocks_per_cu<Gm, G, TWREG, PF, WPE>;
   return v;
 }
 

@@ -414,6 +414,16 @@ static int mixed_batch_blocks_per_cu() {
   return 1;  // flat launch: the grid is the item count
 }
 
+template <class H, bool PF, bool NT, int NW>
+static int mixed_grid_blocks_per_cu() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &nb, reinterpret_cast<const void *>(&ols_mixed4096_kernel<H, PF, NT, NW>), 64 * NW,
+          0) != hipSuccess)
+    return 0;
+  return nb;
+}
+
 template <class H, bool PF = false, bool NT = true, int NW = 8>
 static OlsVariant make_mixed(const char *name, int precision) {
   OlsVariant v{};
@@ -433,6 +443,7 @@ static OlsVariant make_mixed(const char *name, int precision) {
   v.launch = &launch_mixed4096<H, PF, NT, NW>;
   v.launch_batch = &launch_mixed4096_batch<H, PF, NT, NW>;
   v.batch_blocks_per_cu = &mixed_batch_blocks_per_cu<H, PF, NT, NW>;
+  v.grid_blocks_per_cu = &mixed_grid_blocks_per_cu<H, PF, NT, NW>;
   return v;
 }
 

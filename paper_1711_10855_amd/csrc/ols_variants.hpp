@@ -61,6 +61,7 @@ struct OlsVariant {
   hipError_t (*launch)(const OlsArgs &, hipStream_t);
   hipError_t (*launch_batch)(const BatchArgs &, hipStream_t);
   int (*batch_blocks_per_cu)();
+  int (*grid_blocks_per_cu)();  // occupancy of the single-spectrum kernel
 };
 
 const OlsVariant *fp32_variants(int *count);

@@ -37,6 +37,8 @@ struct fdas_plan_s {
   uint64_t use_clock = 0;
   hipStream_t cap_stream = nullptr;
   int cus = 0;
+  bool zpb_forced = false;  // FDAS_ZPB or the autotuner fixed it
+  int slots = 0;            // concurrently resident blocks of the grid kernel
 };
 
 static constexpr size_t kMaxGraphs = 8;
@@ -269,6 +271,7 @@ static int build_plan_with(fdas_plan_t *out, const fdas_params &p, int nz, int d
     if (v > 0) pl->zpb = v;
   }
   if (force_zpb > 0) pl->zpb = force_zpb;
+  pl->zpb_forced = force_zpb > 0 || (std::getenv("FDAS_ZPB") && std::atoi(std::getenv("FDAS_ZPB")) > 0);
 
   void *h = nullptr;
   const size_t hbytes = (size_t)nz * (p.m + 1) * 16;
@@ -361,12 +364,41 @@ int plan_bank_natural(fdas_plan_t pl, void *dst, hipStream_t s) {
   return FDAS_OK;
 }
 
+// Templates per work unit for a grid of nsb segment groups: the grid runs in
+// ceil(blocks / slots) rounds, each as long as one unit (zpb inverse FFTs plus
+// about one forward FFT); pick the group count that minimises that product.
+static int launch_zpb(fdas_plan_t pl, int64_t nsb) {
+  if (pl->zpb_forced) return pl->zpb;
+  if (!pl->slots) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, pl->device) != hipSuccess)
+      return pl->zpb;
+    const int per = pl->var->grid_blocks_per_cu ? pl->var->grid_blocks_per_cu() : 0;
+    if (per <= 0 || cus <= 0) return pl->zpb;
+    pl->slots = cus * per;
+  }
+  double best = 0.0;
+  int best_zpb = pl->zpb;
+  for (int ng = 1; ng <= std::min(pl->nz, 16); ++ng) {
+    const int zpb = (pl->nz + ng - 1) / ng;
+    const int groups = (pl->nz + zpb - 1) / zpb;
+    const double rounds = std::ceil((double)(nsb * groups) / (double)pl->slots);
+    const double cost = rounds * (zpb + 1.0);
+    if (ng == 1 || cost < best * 0.999) {
+      best = cost;
+      best_zpb = zpb;
+    }
+  }
+  return best_zpb;
+}
+
 int plan_convolve(fdas_plan_t pl, const void *spec, int64_t nbins, float *power, int64_t ld,
                   hipStream_t s) {
   const int64_t nseg = (nbins + pl->U - 1) / pl->U;
   if (nseg > INT_MAX / 2) return set_error(FDAS_ERR_UNSUPPORTED, "nbins %lld too large", (long long)nbins);
   const int64_t nsb = (nseg + pl->var->G - 1) / pl->var->G;
-  const int64_t nzg = (pl->nz + pl->zpb - 1) / pl->zpb;
+  const int zpb = launch_zpb(pl, nsb);
+  const int64_t nzg = (pl->nz + zpb - 1) / zpb;
   if (nsb * nzg > (int64_t)UINT_MAX)
     return set_error(FDAS_ERR_UNSUPPORTED, "grid of %lld blocks too large", (long long)(nsb * nzg));
   OlsArgs a;
@@ -380,7 +412,7 @@ int plan_convolve(fdas_plan_t pl, const void *spec, int64_t nbins, float *power,
   a.U = pl->U;
   a.half = pl->m / 2;
   a.nz = pl->nz;
-  a.zpb = pl->zpb;
+  a.zpb = zpb;
   a.bank_log2 = 0;
   while ((1 << a.bank_log2) < pl->L) ++a.bank_log2;
   a.consts = pl->consts;

@@ -106,3 +106,23 @@ def test_mixed_batch_matches_oracle(gpu):
         print(f"fp16 batch nbins={n} zmax={z}: {err:.3e}")
         assert err <= TOL_MIXED
         assert np.all(o[:, n:] == -5.0)
+
+
+def _mixed_variants():
+    from paper_1711_10855_amd import fdas
+    return [n for n in fdas.kernel_variants(4096, "fp16")] + \
+        [n for n in fdas.kernel_variants(4096, "bf16")]
+
+
+@pytest.mark.parametrize("name", _mixed_variants())
+def test_every_mixed_variant(gpu, name, monkeypatch):
+    prec = "bf16" if name.startswith("bf16") else "fp16"
+    monkeypatch.setenv("FDAS_VARIANT", name)
+    a = synth.small_random_spectrum(2 * 3840 + 999, seed=31)
+    ref = oracle.plane_direct(a, 8.0, 2.0, 256)
+    with gpu.Plan(8.0, 2.0, 256, 4096, prec) as p:
+        assert p.info.kernel == name
+        out = p.convolve(to_dev(a)).cpu().numpy()
+    err = rel_err(out, ref)
+    print(f"{name}: {err:.3e}")
+    assert err <= (TOL_MIXED if prec == "fp16" else 2e-2)
