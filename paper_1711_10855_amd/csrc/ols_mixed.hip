@@ -62,10 +62,13 @@ struct Vec<__bf16> {
 };
 
 // One LDS buffer: two planes (re, im) of 256 rows x 16 values. Row r starts
-// at r*16 + (r/16)*8 halves; the two 8-value chunks of a row are swapped
-// when bit 3 of the row is set. Reads of one chunk by 16 consecutive rows and
-// writes of 4 values by rows 16 apart are then free of bank conflicts.
-constexpr int kPlane = 256 * 16 + 16 * 8;  // halves per plane
+// at r*16 + (r/16)*8 halves (16 bytes of padding per 16 rows) and its two
+// 8-value chunks are swapped when bit 2 of the row is set; planes are 64
+// bytes longer than their rows. Every access is a 16-byte chunk: operand
+// reads by 16 consecutive rows, stage-output writes by rows 16 apart, and
+// the per-wave output staging; with 128 bytes served per LDS cycle none of
+// them has a bank conflict.
+constexpr int kPlane = 256 * 16 + 16 * 8 + 32;  // halves per plane
 
 // Plan-time constants of the L = 4096 mixed kernel (bytes):
 //   [17 matrices][64 lanes][B1, B2][8 x 16-bit]  matrix 0: plain inverse DFT16,
@@ -76,14 +79,51 @@ constexpr int kConstB = 17 * 64 * 2 * 16;
 constexpr int kConstBytes = kConstB + (64 * 4 + 16 * 64 * 4) * 8;
 
 __device__ __forceinline__ int lds_idx(int row, int e) {
-  return row * 16 + (row >> 4) * 8 + ((((e >> 3) ^ (row >> 3)) & 1) << 3) + (e & 7);
+  return row * 16 + (row >> 4) * 8 + ((((e >> 3) ^ (row >> 2)) & 1) << 3) + (e & 7);
+}
+// start of row r (halves), chunk swizzle not applied (output staging)
+__device__ __forceinline__ int lds_row(int row) { return row * 16 + (row >> 4) * 8; }
+
+// Ordering of LDS traffic inside one wave (no workgroup barrier).
+__device__ __forceinline__ void wave_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// A lane holds four consecutive values (rows 4g..4g+3 of the next stage's
+// vector) of both planes. Lanes g and g^1 (16 apart) swap halves so that an
+// even g holds eight real values and an odd g eight imaginary values, then
+// each writes one 16-byte chunk: plane g&1, chunk g>>1 of row `row`.
+template <class H>
+__device__ __forceinline__ void store_stage(H *buf, int row, int g, const float (&re)[4],
+                                            const float (&im)[4]) {
+  typename Vec<H>::v4 r4 = {(H)re[0], (H)re[1], (H)re[2], (H)re[3]};
+  typename Vec<H>::v4 i4 = {(H)im[0], (H)im[1], (H)im[2], (H)im[3]};
+  const u32x2 rb = __builtin_bit_cast(u32x2, r4);
+  const u32x2 ib = __builtin_bit_cast(u32x2, i4);
+  const bool odd = g & 1;
+  const u32x2 send = odd ? rb : ib;
+  u32x2 recv;
+  // bit-mode swizzle: and_mask 0x1f, or_mask 0, xor_mask 0x10 (lane ^ 16)
+  recv.x = __builtin_amdgcn_ds_swizzle(send.x, 0x401f);
+  recv.y = __builtin_amdgcn_ds_swizzle(send.y, 0x401f);
+  u32x4 chunk;
+  if (odd) chunk = (u32x4){recv.x, recv.y, ib.x, ib.y};
+  else chunk = (u32x4){rb.x, rb.y, recv.x, recv.y};
+  *reinterpret_cast<u32x4 *>(buf + (g & 1) * kPlane + lds_idx(row, 8 * (g >> 1))) = chunk;
 }
 
 template <class H>
-__device__ __forceinline__ void store4(H *plane, int row, int e0, float a, float b, float c,
-                                       float d) {
-  typename Vec<H>::v4 v = {(H)a, (H)b, (H)c, (H)d};
-  *reinterpret_cast<typename Vec<H>::v4 *>(plane + lds_idx(row, e0)) = v;
+__device__ __forceinline__ void store8(H *plane, int row, int e0, const c32 *x, bool imag,
+                                       float scale) {
+  typename Vec<H>::v8 v;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) v[k] = (H)((imag ? x[k].y : x[k].x) * scale);
+  *reinterpret_cast<typename Vec<H>::v8 *>(plane + lds_idx(row, e0)) = v;
 }
 
 template <class H>
@@ -222,13 +262,12 @@ __device__ __forceinline__ void mixed_unit(const MixedConsts<H, NW> &K,
   const float xscale = ldexpf(1.0f, 3 - ex);
   // power = |y'|^2 * 2^(-2 (a + b)) with a = 3 - ex, b = bank_log2
   const float pscale = ldexpf(1.0f, -2 * (3 - ex + bank_log2));
+  if (fw) {
 #pragma unroll
-  for (int e0 = 0; e0 < 16; e0 += 4) {
-    if (!fw) break;
-    store4<H>(Xp, t, e0, x[e0].x * xscale, x[e0 + 1].x * xscale, x[e0 + 2].x * xscale,
-              x[e0 + 3].x * xscale);
-    store4<H>(Xp + kPlane, t, e0, x[e0].y * xscale, x[e0 + 1].y * xscale, x[e0 + 2].y * xscale,
-              x[e0 + 3].y * xscale);
+    for (int e0 = 0; e0 < 16; e0 += 8) {
+      store8<H>(Xp, t, e0, &x[e0], false, xscale);
+      store8<H>(Xp + kPlane, t, e0, &x[e0], true, xscale);
+    }
   }
 
   __syncthreads();  // X complete
@@ -274,9 +313,7 @@ __device__ __forceinline__ void mixed_unit(const MixedConsts<H, NW> &K,
         orr[i] = v.x;
         oii[i] = v.y;
       }
-      const int orow = 16 * c + k0;  // stage 1' butterfly (k0, n2 = c)
-      store4<H>(Ea, orow, 4 * g, orr[0], orr[1], orr[2], orr[3]);
-      store4<H>(Ea + kPlane, orow, 4 * g, oii[0], oii[1], oii[2], oii[3]);
+      store_stage<H>(Ea, 16 * c + k0, g, orr, oii);  // stage 1' butterfly (k0, n2 = c)
     }
     __syncthreads();
     // ---- stage 1' (tiles n2 = TPW w + j; rows k0 = c) -------------------------
@@ -296,13 +333,14 @@ __device__ __forceinline__ void mixed_unit(const MixedConsts<H, NW> &K,
         orr[i] = v.x;
         oii[i] = v.y;
       }
-      const int orow = 16 * c + n2;  // stage 0' butterfly (n1 = c, n2)
-      store4<H>(Eb, orow, 4 * g, orr[0], orr[1], orr[2], orr[3]);
-      store4<H>(Eb + kPlane, orow, 4 * g, oii[0], oii[1], oii[2], oii[3]);
+      store_stage<H>(Eb, 16 * c + n2, g, orr, oii);  // stage 0' butterfly (n1 = c, n2)
     }
     __syncthreads();
     // ---- stage 0' (tiles n1 = TPW w + j; rows n2 = c) + |.|^2 -----------------
-    float *prow = power + (int64_t)(iz - row_base) * ld;
+    // The wave's TPW tiles cover, for every n0 = c, the 16 TPW consecutive
+    // outputs 256 c + 16 TPW w + [0, 16 TPW). The powers are staged in the
+    // Ea rows this wave alone writes (16 c + TPW w + j, both planes; free
+    // until its own next stage 2') and stored as whole 128-byte lines.
 #pragma unroll
     for (int j = 0; j < TPW; ++j) {
       const int n1 = TPW * w + j;
@@ -311,15 +349,27 @@ __device__ __forceinline__ void mixed_unit(const MixedConsts<H, NW> &K,
       f4 zero = {0.f, 0.f, 0.f, 0.f};
       const f4 dr = Vec<H>::mfma(a, bT1[j], zero);
       const f4 di = Vec<H>::mfma(a, bT2[j], zero);
-      // lane holds y[256 c + 16 n1 + 4g + i], i = 0..3: one 16-byte store;
-      // the four lane groups of a column write 64 contiguous bytes
-      if (active) {
-        const int o0 = 256 * c + 16 * n1 + 4 * g;
-        const int64_t r0 = (int64_t)s * U + o0 - half;
-        f4 pw;
+      f4 pw;  // y[256 c + 16 n1 + 4 g + i], staged as float 16 j + 4 g + i of line c
 #pragma unroll
-        for (int i = 0; i < 4; ++i) pw[i] = (dr[i] * dr[i] + di[i] * di[i]) * pscale;
-        if (o0 >= half && o0 + 3 < half + U && r0 + 3 < nbins && ((reinterpret_cast<uintptr_t>(prow + r0) & 15) == 0)) {
+      for (int i = 0; i < 4; ++i) pw[i] = (dr[i] * dr[i] + di[i] * di[i]) * pscale;
+      H *srow = Ea + (g >> 1) * kPlane + lds_row(16 * c + TPW * w + j);
+      *reinterpret_cast<f4 *>(srow + 8 * (g & 1)) = pw;
+    }
+    wave_fence();
+    if (active) {
+      float *prow = power + (int64_t)(iz - row_base) * ld;
+      constexpr int PARTS = 4 * TPW;       // 16-byte parts per line
+      constexpr int LINES = 64 / PARTS;    // lines per store instruction
+#pragma unroll
+      for (int k = 0; k < 16 / LINES; ++k) {
+        const int cl = lane / PARTS + k * LINES;
+        const int b = lane % PARTS;
+        const H *srow = Ea + ((b >> 1) & 1) * kPlane + lds_row(16 * cl + TPW * w + (b >> 2));
+        const f4 pw = *reinterpret_cast<const f4 *>(srow + 8 * (b & 1));
+        const int o0 = 256 * cl + 16 * TPW * w + 4 * b;
+        const int64_t r0 = (int64_t)s * U + o0 - half;
+        if (o0 >= half && o0 + 3 < half + U && r0 + 3 < nbins &&
+            ((reinterpret_cast<uintptr_t>(prow + r0) & 15) == 0)) {
           if constexpr (NT) __builtin_nontemporal_store(pw, reinterpret_cast<f4 *>(prow + r0));
           else *reinterpret_cast<f4 *>(prow + r0) = pw;
         } else {
@@ -331,6 +381,7 @@ __device__ __forceinline__ void mixed_unit(const MixedConsts<H, NW> &K,
         }
       }
     }
+    wave_fence();
   }
 }
 

@@ -141,7 +141,9 @@ def main():
         tj = os.path.join(ROOT, "profiles", "traffic.json")
         rows = []
         if os.path.exists(tj):
-            rows = [r for r in json.load(open(tj)) if r.get("profile") != a.name]
+            rows = [r for r in json.load(open(tj))
+                    if r.get("profile") != a.name
+                    and (r.get("kernel"), r.get("workload")) != (a.variant, a.workload)]
         row["kernel_symbol"] = kname.split("(")[0] if kname else None
         rows.append(row)
         with open(tj, "w") as f:
