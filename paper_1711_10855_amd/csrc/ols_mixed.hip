@@ -22,10 +22,16 @@
 // (output), the inverse DFT (eq. 3 with the opposite sign, unnormalised) is
 //   y[n] = sum_k0 w16^(n0 k0) w256^(n1 k0) w4096^(n2 k0)
 //          sum_k1 w16^(n1 k1) w256^(n2 k1) sum_k2 w16^(n2 k2) Y[k],
-// with wN = exp(+2 pi i / N). Stage 2': tile k0, rows k1, columns n2, then
-// twiddle w256^(k1 n2). Stage 1': tile n2, rows k0, columns n1, then
-// twiddle w4096^(k0 n2). Stage 0': tile n1, rows n2, columns n0, with the
-// factor w256^(n1 k0) folded into that tile's B matrix.
+// with wN = exp(+2 pi i / N). Stage 2': tile k0, rows k1, K = k2, columns n2.
+// Stage 1': tile n2, rows k0, K = k1, columns n1. Stage 0': tile n1, rows n2,
+// K = k0, columns n0. Every twiddle depends on one stage's tile and on either
+// its K index or its column, never on its row, so each is folded into that
+// tile's B matrix: w4096^(n2 k0) into stage 2' (tile k0, column n2),
+// w256^(n2 k1) into stage 1' (tile n2, K k1), w256^(n1 k0) into stage 0'
+// (tile n1, K k0). The inverse then has no scalar twiddle multiplies at all.
+// Stages 1' and 0' use the same family of matrices, P_p[K k][column c] =
+// w256^(k (16 c + p)), with p the tile; stage 2' uses
+// Q_t[k][c] = w4096^(c (256 k + t)).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -62,73 +68,71 @@ struct Vec<__bf16> {
 };
 
 // One LDS buffer: two planes (re, im) of 256 rows x 16 values. Row r starts
-// at r*16 + (r/16)*8 halves (16 bytes of padding per 16 rows) and its two
-// 8-value chunks are swapped when bit 2 of the row is set; planes are 64
-// bytes longer than their rows. Every access is a 16-byte chunk: operand
-// reads by 16 consecutive rows, stage-output writes by rows 16 apart, and
-// the per-wave output staging; with 128 bytes served per LDS cycle none of
-// them has a bank conflict.
+// at r*16 + (r/16)*8 halves (16 bytes of padding per 16 rows); its two
+// 8-value chunks are swapped when bit 2 of the row is set, and the two
+// 4-value halves of each chunk when bit 7 is set. Operand reads take one
+// 16-byte chunk from 16 consecutive rows; stage outputs are written as
+// 8-byte groups of four values to rows 16 apart. With 128 bytes served per
+// LDS cycle neither has a bank conflict. A chunk read from a row with bit 7
+// set holds its values in the order 4..7, 0..3; rows 16 t + c of tile t
+// share that bit (bit 3 of t), and the tile's B matrix and bank rows are
+// stored in the same order.
 constexpr int kPlane = 256 * 16 + 16 * 8 + 32;  // halves per plane
 
-// Plan-time constants of the L = 4096 mixed kernel (bytes):
-//   [17 matrices][64 lanes][B1, B2][8 x 16-bit]  matrix 0: plain inverse DFT16,
-//                                                 matrix 1 + n1: w256^(n1 k0) folded in
-//   then FP32 complex twiddles: [64 lanes][4] w256^((4g+i) c)
-//                               [16 tiles][64 lanes][4] w4096^((4g+i) n2)
-constexpr int kConstB = 17 * 64 * 2 * 16;
-constexpr int kConstBytes = kConstB + (64 * 4 + 16 * 64 * 4) * 8;
+// Plan-time constants of the L = 4096 mixed kernel: the B operands of the
+// two matrix families, [family Q, P][16 tiles][64 lanes][B1, B2][8 x 16-bit].
+constexpr int kConstBytes = 2 * 16 * 64 * 2 * 16;
 
 __device__ __forceinline__ int lds_idx(int row, int e) {
-  return row * 16 + (row >> 4) * 8 + ((((e >> 3) ^ (row >> 2)) & 1) << 3) + (e & 7);
+  return row * 16 + (row >> 4) * 8 + ((((e >> 3) ^ (row >> 2)) & 1) << 3) +
+         ((((e >> 2) ^ (row >> 7)) & 1) << 2) + (e & 3);
 }
-// start of row r (halves), chunk swizzle not applied (output staging)
-__device__ __forceinline__ int lds_row(int row) { return row * 16 + (row >> 4) * 8; }
-
-// Ordering of LDS traffic inside one wave (no workgroup barrier).
-__device__ __forceinline__ void wave_fence() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+// start of the chunk that holds values 8h .. 8h+7 of row r
+__device__ __forceinline__ int lds_chunk(int row, int h) {
+  return row * 16 + (row >> 4) * 8 + (((h ^ (row >> 2)) & 1) << 3);
 }
 
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-// A lane holds four consecutive values (rows 4g..4g+3 of the next stage's
-// vector) of both planes. Lanes g and g^1 (16 apart) swap halves so that an
-// even g holds eight real values and an odd g eight imaginary values, then
-// each writes one 16-byte chunk: plane g&1, chunk g>>1 of row `row`.
+// A lane holds four consecutive values (4g .. 4g+3 of row `row` of the next
+// stage) of both planes; each plane's four go out as one 8-byte write.
 template <class H>
-__device__ __forceinline__ void store_stage(H *buf, int row, int g, const float (&re)[4],
-                                            const float (&im)[4]) {
-  typename Vec<H>::v4 r4 = {(H)re[0], (H)re[1], (H)re[2], (H)re[3]};
-  typename Vec<H>::v4 i4 = {(H)im[0], (H)im[1], (H)im[2], (H)im[3]};
-  const u32x2 rb = __builtin_bit_cast(u32x2, r4);
-  const u32x2 ib = __builtin_bit_cast(u32x2, i4);
-  const bool odd = g & 1;
-  const u32x2 send = odd ? rb : ib;
-  u32x2 recv;
-  // bit-mode swizzle: and_mask 0x1f, or_mask 0, xor_mask 0x10 (lane ^ 16)
-  recv.x = __builtin_amdgcn_ds_swizzle(send.x, 0x401f);
-  recv.y = __builtin_amdgcn_ds_swizzle(send.y, 0x401f);
-  u32x4 chunk;
-  if (odd) chunk = (u32x4){recv.x, recv.y, ib.x, ib.y};
-  else chunk = (u32x4){rb.x, rb.y, recv.x, recv.y};
-  *reinterpret_cast<u32x4 *>(buf + (g & 1) * kPlane + lds_idx(row, 8 * (g >> 1))) = chunk;
+__device__ __forceinline__ void store_stage(H *buf, int row, int g, const f4 &re,
+                                            const f4 &im) {
+  const typename Vec<H>::v4 r4 = {(H)re[0], (H)re[1], (H)re[2], (H)re[3]};
+  const typename Vec<H>::v4 i4 = {(H)im[0], (H)im[1], (H)im[2], (H)im[3]};
+  const int o = lds_idx(row, 4 * g);
+  *reinterpret_cast<typename Vec<H>::v4 *>(buf + o) = r4;
+  *reinterpret_cast<typename Vec<H>::v4 *>(buf + kPlane + o) = i4;
 }
 
+// Values e0 .. e0+7 of row `row` (one plane), as two 8-byte groups.
 template <class H>
 __device__ __forceinline__ void store8(H *plane, int row, int e0, const c32 *x, bool imag,
                                        float scale) {
-  typename Vec<H>::v8 v;
 #pragma unroll
-  for (int k = 0; k < 8; ++k) v[k] = (H)((imag ? x[k].y : x[k].x) * scale);
-  *reinterpret_cast<typename Vec<H>::v8 *>(plane + lds_idx(row, e0)) = v;
+  for (int q = 0; q < 2; ++q) {
+    typename Vec<H>::v4 v;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = (H)((imag ? x[4 * q + k].y : x[4 * q + k].x) * scale);
+    *reinterpret_cast<typename Vec<H>::v4 *>(plane + lds_idx(row, e0 + 4 * q)) = v;
+  }
 }
 
 template <class H>
-__device__ __forceinline__ typename Vec<H>::v8 load8(const H *plane, int row, int e0) {
-  return *reinterpret_cast<const typename Vec<H>::v8 *>(plane + lds_idx(row, e0));
+__device__ __forceinline__ typename Vec<H>::v8 load8(const H *plane, int row, int h) {
+  return *reinterpret_cast<const typename Vec<H>::v8 *>(plane + lds_chunk(row, h));
+}
+
+// Lanes c and c ^ 8 of each 16-lane row exchange one float: lanes in the
+// 4-lane banks selected by `bank_mask` take the partner's `src`, the others
+// keep `keep` (DPP row rotate by 8).
+template <int BANK_MASK>
+__device__ __forceinline__ float swap8(float keep, float src) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, keep),
+                                                               __builtin_bit_cast(int, src),
+                                                               0x128, 0xf, BANK_MASK, false));
 }
 
 // forward FFT geometry: 4096 = 16 * 16 * 16 over 256 threads (as the FP32 kernel)
@@ -143,17 +147,16 @@ __device__ __forceinline__ int fwd_addr(int t, int n) {
 __device__ __forceinline__ int fpad(int a) { return a + (a >> 4); }
 
 constexpr int kMixF32 = (4096 + 4096 / 16) * 8;
-constexpr int kMix16 = 3 * 2 * kPlane * 2;
+constexpr int kMix16 = 2 * 2 * kPlane * 2;  // stage buffers Ea, Eb (X is staged in Eb)
 constexpr int kMixSmem = kMixF32 > kMix16 ? kMixF32 : kMix16;
 
-// Per-lane constants, loaded once per block from the plan-time table.
+// Per-lane constants, loaded once per block from the plan-time table: the B
+// operands of the wave's TPW tiles in each family.
 template <class H, int NW>
 struct MixedConsts {
   static constexpr int TPW = 16 / NW;
-  typename Vec<H>::v8 bF1, bF2;            // plain inverse DFT16
-  typename Vec<H>::v8 bT1[TPW], bT2[TPW];  // stage 0' tiles n1 = TPW w + j
-  c32 tw1[4];                              // after stage 2': w256^((4g+i) c)
-  c32 tw2[TPW][4];                         // after stage 1': w4096^((4g+i) n2)
+  typename Vec<H>::v8 q1[TPW], q2[TPW];  // stage 2' tiles k0 = TPW w + j
+  typename Vec<H>::v8 p1[TPW], p2[TPW];  // stage 1' tiles n2 and stage 0' tiles n1 = TPW w + j
 };
 
 template <class H, int NW>
@@ -163,26 +166,20 @@ __device__ __forceinline__ void load_mixed_consts(MixedConsts<H, NW> &K,
   typedef typename Vec<H>::v8 v8;
   constexpr int TPW = 16 / NW;
   const v8 *cb = reinterpret_cast<const v8 *>(consts);
-  K.bF1 = cb[(0 * 64 + lane) * 2];
-  K.bF2 = cb[(0 * 64 + lane) * 2 + 1];
 #pragma unroll
   for (int j = 0; j < TPW; ++j) {
-    K.bT1[j] = cb[((1 + TPW * w + j) * 64 + lane) * 2];
-    K.bT2[j] = cb[((1 + TPW * w + j) * 64 + lane) * 2 + 1];
-  }
-  const c32 *ctw = reinterpret_cast<const c32 *>(consts + kConstB);
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    K.tw1[i] = ctw[lane * 4 + i];
-#pragma unroll
-    for (int j = 0; j < TPW; ++j) K.tw2[j][i] = ctw[256 + ((TPW * w + j) * 64 + lane) * 4 + i];
+    const int tile = TPW * w + j;
+    K.q1[j] = cb[((0 * 16 + tile) * 64 + lane) * 2];
+    K.q2[j] = cb[((0 * 16 + tile) * 64 + lane) * 2 + 1];
+    K.p1[j] = cb[((1 * 16 + tile) * 64 + lane) * 2];
+    K.p2[j] = cb[((1 * 16 + tile) * 64 + lane) * 2 + 1];
   }
 }
 
 // One work unit of the mixed kernel: segment s, bank rows [z0, z1), plane
 // rows iz - row_base. Every thread of the block calls it (barriers inside).
 template <class H, bool PF, bool NT, int NW>
-__device__ __forceinline__ void mixed_unit(const MixedConsts<H, NW> &K,
+__device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ consts,
                                            const c32 *__restrict__ spec, int64_t nbins,
                                            const H *__restrict__ bank, const c32 *__restrict__ tw,
                                            float *__restrict__ power, int64_t ld, int s,
@@ -192,19 +189,15 @@ __device__ __forceinline__ void mixed_unit(const MixedConsts<H, NW> &K,
   typedef typename Vec<H>::v8 v8;
   constexpr int L = 4096;
   constexpr int TPW = 16 / NW;
+  static_assert(TPW % 2 == 0, "output lines are formed from pairs of stage-0' tiles");
   c32 *fbuf = reinterpret_cast<c32 *>(smem);
-  H *Xp = reinterpret_cast<H *>(smem);
-  H *Ea = Xp + 2 * kPlane;
+  H *Ea = reinterpret_cast<H *>(smem);
   H *Eb = Ea + 2 * kPlane;
+  H *Xp = Eb;  // X passes through Eb once; first overwritten by stage 1' of the first template
   const int t = threadIdx.x;
   const int lane = t & 63, w = t >> 6;
   const int g = lane >> 4, c = lane & 15, h = g & 1;
   const int64_t seg0 = (int64_t)s * U - half;
-  const v8 &bF1 = K.bF1, &bF2 = K.bF2;
-  const auto &bT1 = K.bT1;
-  const auto &bT2 = K.bT2;
-  const auto &tw1 = K.tw1;
-  const auto &tw2 = K.tw2;
 
   // ---- forward FFT, FP32, decimation in frequency, threads 0..255 ---------
   // (threads above 255 only join the barriers)
@@ -269,12 +262,25 @@ __device__ __forceinline__ void mixed_unit(const MixedConsts<H, NW> &K,
       store8<H>(Xp + kPlane, t, e0, &x[e0], true, xscale);
     }
   }
-
   __syncthreads();  // X complete
 
-  const H *Xre = Xp, *Xim = Xp + kPlane;
-  // bank rows are read one template ahead (tiles k0 = 4w + j, rows 16 k0 + c, chunk h)
-  // re lanes compute xr*tr + xi*(-ti), im lanes xr*ti + xi*tr: plane offsets
+  // The B operands are loaded only now, so that they do not hold registers
+  // during the forward FFT.
+  MixedConsts<H, NW> K;
+  load_mixed_consts<H, NW>(K, consts, lane, w);
+
+  // X stays in registers for the whole template loop: rows 16 k0 + c of the
+  // wave's tiles k0 = TPW w + j, chunk h, both planes.
+  v8 xr[TPW], xi[TPW];
+#pragma unroll
+  for (int j = 0; j < TPW; ++j) {
+    const int row = 16 * (TPW * w + j) + c;
+    xr[j] = load8<H>(Xp, row, h);
+    xi[j] = load8<H>(Xp + kPlane, row, h);
+  }
+
+  // Bank rows for the same lanes; re lanes (g < 2) compute xr*tr + xi*(-ti),
+  // im lanes xr*ti + xi*tr: plane offsets.
   const int pu = (g < 2 ? 0 : 1) * L, pv = (g < 2 ? 2 : 0) * L;
   v8 btr[TPW], bti[TPW];
   auto load_bank = [&](int iz) {
@@ -286,121 +292,105 @@ __device__ __forceinline__ void mixed_unit(const MixedConsts<H, NW> &K,
       bti[j] = *reinterpret_cast<const v8 *>(brow + pv + row * 16 + 8 * h);
     }
   };
+
+  // Output addressing. Stage 0' gives lane (g, c) of tile n1 = TPW w + j the
+  // powers y[256 c + 16 n1 + 4 g + i], i < 4. Tiles 2p and 2p + 1 together
+  // cover 32 consecutive outputs (one 128-byte line) per column c; lanes c
+  // and c ^ 8 exchange one tile's values so that each store instruction
+  // writes eight whole lines: instruction 0 columns 0..7, instruction 1
+  // columns 8..15.
+  const bool lo8 = c < 8;
+  int o_st[2];
+  o_st[0] = 256 * (lo8 ? c : c - 8) + 16 * TPW * w + 16 * (lo8 ? 0 : 1) + 4 * g;
+  o_st[1] = 256 * (lo8 ? c + 8 : c) + 16 * TPW * w + 16 * (lo8 ? 0 : 1) + 4 * g;
+
   if (PF && z0 < z1) load_bank(z0);
   for (int iz = z0; iz < z1; ++iz) {
     if (!PF) load_bank(iz);
     // ---- product + stage 2' (tiles k0 = TPW w + j; rows k1 = c; chunk h) ----
     v8 av[TPW];
 #pragma unroll
-    for (int j = 0; j < TPW; ++j) {
-      const int row = 16 * (TPW * w + j) + c;
-      const v8 xr = load8<H>(Xre, row, 8 * h);
-      const v8 xi = load8<H>(Xim, row, 8 * h);
-      av[j] = xr * btr[j] + xi * bti[j];
-    }
+    for (int j = 0; j < TPW; ++j) av[j] = xr[j] * btr[j] + xi[j] * bti[j];
     if (PF && iz + 1 < z1) load_bank(iz + 1);
 #pragma unroll
     for (int j = 0; j < TPW; ++j) {
       const int k0 = TPW * w + j;
-      f4 zero = {0.f, 0.f, 0.f, 0.f};
-      const f4 dr = Vec<H>::mfma(av[j], bF1, zero);
-      const f4 di = Vec<H>::mfma(av[j], bF2, zero);
+      const f4 zero = {0.f, 0.f, 0.f, 0.f};
+      const f4 dr = Vec<H>::mfma(av[j], K.q1[j], zero);
+      const f4 di = Vec<H>::mfma(av[j], K.q2[j], zero);
       // lane holds rows k1 = 4g + i, column n2 = c
-      float orr[4], oii[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const c32 v = cmul({dr[i], di[i]}, tw1[i]);
-        orr[i] = v.x;
-        oii[i] = v.y;
-      }
-      store_stage<H>(Ea, 16 * c + k0, g, orr, oii);  // stage 1' butterfly (k0, n2 = c)
+      store_stage<H>(Ea, 16 * c + k0, g, dr, di);  // stage 1' butterfly (k0, n2 = c)
     }
     __syncthreads();
     // ---- stage 1' (tiles n2 = TPW w + j; rows k0 = c) -------------------------
 #pragma unroll
     for (int j = 0; j < TPW; ++j) {
       const int n2 = TPW * w + j;
-      const int row = 16 * n2 + c;
-      const v8 a = load8<H>(Ea + (g >> 1) * kPlane, row, 8 * h);
-      f4 zero = {0.f, 0.f, 0.f, 0.f};
-      const f4 dr = Vec<H>::mfma(a, bF1, zero);
-      const f4 di = Vec<H>::mfma(a, bF2, zero);
+      const v8 a = load8<H>(Ea + (g >> 1) * kPlane, 16 * n2 + c, h);
+      const f4 zero = {0.f, 0.f, 0.f, 0.f};
+      const f4 dr = Vec<H>::mfma(a, K.p1[j], zero);
+      const f4 di = Vec<H>::mfma(a, K.p2[j], zero);
       // lane holds rows k0 = 4g + i, column n1 = c
-      float orr[4], oii[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const c32 v = cmul({dr[i], di[i]}, tw2[j][i]);
-        orr[i] = v.x;
-        oii[i] = v.y;
-      }
-      store_stage<H>(Eb, 16 * c + n2, g, orr, oii);  // stage 0' butterfly (n1 = c, n2)
+      store_stage<H>(Eb, 16 * c + n2, g, dr, di);  // stage 0' butterfly (n1 = c, n2)
     }
     __syncthreads();
-    // ---- stage 0' (tiles n1 = TPW w + j; rows n2 = c) + |.|^2 -----------------
-    // The wave's TPW tiles cover, for every n0 = c, the 16 TPW consecutive
-    // outputs 256 c + 16 TPW w + [0, 16 TPW). The powers are staged in the
-    // Ea rows this wave alone writes (16 c + TPW w + j, both planes; free
-    // until its own next stage 2') and stored as whole 128-byte lines.
+    // ---- stage 0' (tiles n1 = TPW w + j; rows n2 = c) + |.|^2 + store --------
+    float *prow = power + (int64_t)(iz - row_base) * ld;
 #pragma unroll
-    for (int j = 0; j < TPW; ++j) {
-      const int n1 = TPW * w + j;
-      const int row = 16 * n1 + c;
-      const v8 a = load8<H>(Eb + (g >> 1) * kPlane, row, 8 * h);
-      f4 zero = {0.f, 0.f, 0.f, 0.f};
-      const f4 dr = Vec<H>::mfma(a, bT1[j], zero);
-      const f4 di = Vec<H>::mfma(a, bT2[j], zero);
-      f4 pw;  // y[256 c + 16 n1 + 4 g + i], staged as float 16 j + 4 g + i of line c
+    for (int p = 0; p < TPW / 2; ++p) {
+      f4 pw[2];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) pw[i] = (dr[i] * dr[i] + di[i] * di[i]) * pscale;
-      H *srow = Ea + (g >> 1) * kPlane + lds_row(16 * c + TPW * w + j);
-      *reinterpret_cast<f4 *>(srow + 8 * (g & 1)) = pw;
-    }
-    wave_fence();
-    if (active) {
-      float *prow = power + (int64_t)(iz - row_base) * ld;
-      constexpr int PARTS = 4 * TPW;       // 16-byte parts per line
-      constexpr int LINES = 64 / PARTS;    // lines per store instruction
+      for (int jj = 0; jj < 2; ++jj) {
+        const int j = 2 * p + jj;
+        const int n1 = TPW * w + j;
+        const v8 a = load8<H>(Eb + (g >> 1) * kPlane, 16 * n1 + c, h);
+        const f4 zero = {0.f, 0.f, 0.f, 0.f};
+        const f4 dr = Vec<H>::mfma(a, K.p1[j], zero);
+        const f4 di = Vec<H>::mfma(a, K.p2[j], zero);
 #pragma unroll
-      for (int k = 0; k < 16 / LINES; ++k) {
-        const int cl = lane / PARTS + k * LINES;
-        const int b = lane % PARTS;
-        const H *srow = Ea + ((b >> 1) & 1) * kPlane + lds_row(16 * cl + TPW * w + (b >> 2));
-        const f4 pw = *reinterpret_cast<const f4 *>(srow + 8 * (b & 1));
-        const int o0 = 256 * cl + 16 * TPW * w + 4 * b;
-        const int64_t r0 = (int64_t)s * U + o0 - half;
-        if (o0 >= half && o0 + 3 < half + U && r0 + 3 < nbins &&
-            ((reinterpret_cast<uintptr_t>(prow + r0) & 15) == 0)) {
-          if constexpr (NT) __builtin_nontemporal_store(pw, reinterpret_cast<f4 *>(prow + r0));
-          else *reinterpret_cast<f4 *>(prow + r0) = pw;
-        } else {
+        for (int i = 0; i < 4; ++i) pw[jj][i] = (dr[i] * dr[i] + di[i] * di[i]) * pscale;
+      }
+      f4 st[2];
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int o = o0 + i;
-            if (o >= half && o < half + U && r0 + i < nbins) prow[r0 + i] = pw[i];
+      for (int i = 0; i < 4; ++i) {
+        st[0][i] = swap8<0xc>(pw[0][i], pw[1][i]);  // lanes c >= 8 take tile 2p+1 of c - 8
+        st[1][i] = swap8<0x3>(pw[1][i], pw[0][i]);  // lanes c < 8 take tile 2p of c + 8
+      }
+      if (active) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int o0 = o_st[q] + 32 * p;
+          const int64_t r0 = (int64_t)s * U + o0 - half;
+          if (o0 >= half && o0 + 3 < half + U && r0 + 3 < nbins &&
+              ((reinterpret_cast<uintptr_t>(prow + r0) & 15) == 0)) {
+            if constexpr (NT) __builtin_nontemporal_store(st[q], reinterpret_cast<f4 *>(prow + r0));
+            else *reinterpret_cast<f4 *>(prow + r0) = st[q];
+          } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int o = o0 + i;
+              if (o >= half && o < half + U && r0 + i < nbins) prow[r0 + i] = st[q][i];
+            }
           }
         }
       }
     }
-    wave_fence();
   }
 }
 
-template <class H, bool PF, bool NT, int NW>
-__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW == 8 ? 4 : 2)))
+template <class H, bool PF, bool NT, int NW, int OCC>
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(OCC, OCC)))
     ols_mixed4096_kernel(const c32 *__restrict__ spec, int64_t nbins, const H *__restrict__ bank,
                          const c32 *__restrict__ tw, const unsigned char *__restrict__ consts,
                          float *__restrict__ power, int64_t ld, int nseg, int U, int half, int nz,
                          int zpb, int nsb, int bank_log2) {
   __shared__ __attribute__((aligned(16))) unsigned char smem[kMixSmem];
   __shared__ float s_max[NW];
-  const int t = threadIdx.x;
-  MixedConsts<H, NW> K;
-  load_mixed_consts<H, NW>(K, consts, t & 63, t >> 6);
   const int sb = blockIdx.x % nsb;
   const int zg = blockIdx.x / nsb;
   const int z0 = zg * zpb;
   const int z1 = min(nz, z0 + zpb);
-  mixed_unit<H, PF, NT, NW>(K, spec, nbins, bank, tw, power, ld, sb, sb < nseg, U, half, z0, z1,
+  mixed_unit<H, PF, NT, NW>(consts, spec, nbins, bank, tw, power, ld, sb, sb < nseg, U, half, z0, z1,
                             0, bank_log2, smem, s_max);
 }
 
@@ -409,15 +399,14 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW
 // dispatcher hands out items in that order as blocks retire. Same body as
 // the single-series kernel; used because the persistent loop around this
 // body does not fit the register budget.
-template <class H, bool PF, bool NT, int NW>
-__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW == 8 ? 4 : 2)))
+template <class H, bool PF, bool NT, int NW, int OCC>
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(OCC, OCC)))
     ols_mixed4096_items_kernel(const SeriesDesc *__restrict__ desc, int nseries,
                                const H *__restrict__ bank, const c32 *__restrict__ tw,
                                const unsigned char *__restrict__ consts, int U, int half, int zpb,
                                int bank_log2) {
   __shared__ __attribute__((aligned(16))) unsigned char smem[kMixSmem];
   __shared__ float s_max[NW];
-  const int t = threadIdx.x;
   const long long item = blockIdx.x;
   int lo = 0, hi = nseries - 1;
   while (lo < hi) {
@@ -431,18 +420,16 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW
   const int sb = (int)(local % d.nseg);
   const int z0 = d.row_off + zg * zpb;
   const int z1 = min(d.row_off + d.nz, z0 + zpb);
-  MixedConsts<H, NW> K;
-  load_mixed_consts<H, NW>(K, consts, t & 63, t >> 6);
-  mixed_unit<H, PF, NT, NW>(K, static_cast<const c32 *>(d.spec), d.nbins, bank, tw, d.power,
+  mixed_unit<H, PF, NT, NW>(consts, static_cast<const c32 *>(d.spec), d.nbins, bank, tw, d.power,
                             d.ld, sb, true, U, half, z0, z1, d.row_off, bank_log2, smem, s_max);
 }
 
-template <class H, bool PF, bool NT, int NW>
+template <class H, bool PF, bool NT, int NW, int OCC>
 static hipError_t launch_mixed4096(const OlsArgs &a, hipStream_t st) {
   const int nsb = a.nseg;
   const int nzg = (a.nz + a.zpb - 1) / a.zpb;
   const long blocks = (long)nsb * nzg;
-  hipLaunchKernelGGL((ols_mixed4096_kernel<H, PF, NT, NW>), dim3((unsigned)blocks), dim3(64 * NW), 0, st,
+  hipLaunchKernelGGL((ols_mixed4096_kernel<H, PF, NT, NW, OCC>), dim3((unsigned)blocks), dim3(64 * NW), 0, st,
                      static_cast<const c32 *>(a.spec), a.nbins, static_cast<const H *>(a.bank),
                      static_cast<const c32 *>(a.tw),
                      static_cast<const unsigned char *>(a.consts), a.power, a.ld, a.nseg, a.U,
@@ -450,32 +437,32 @@ static hipError_t launch_mixed4096(const OlsArgs &a, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <class H, bool PF, bool NT, int NW>
+template <class H, bool PF, bool NT, int NW, int OCC>
 static hipError_t launch_mixed4096_batch(const BatchArgs &a, hipStream_t st) {
   if (a.total > (int64_t)0xffffffffLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((ols_mixed4096_items_kernel<H, PF, NT, NW>), dim3((unsigned)a.total),
+  hipLaunchKernelGGL((ols_mixed4096_items_kernel<H, PF, NT, NW, OCC>), dim3((unsigned)a.total),
                      dim3(64 * NW), 0, st, a.desc, a.nseries, static_cast<const H *>(a.bank),
                      static_cast<const c32 *>(a.tw), static_cast<const unsigned char *>(a.consts),
                      a.U, a.half, a.zpb, a.bank_log2);
   return hipGetLastError();
 }
 
-template <class H, bool PF, bool NT, int NW>
+template <class H, bool PF, bool NT, int NW, int OCC>
 static int mixed_batch_blocks_per_cu() {
   return 1;  // flat launch: the grid is the item count
 }
 
-template <class H, bool PF, bool NT, int NW>
+template <class H, bool PF, bool NT, int NW, int OCC>
 static int mixed_grid_blocks_per_cu() {
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &nb, reinterpret_cast<const void *>(&ols_mixed4096_kernel<H, PF, NT, NW>), 64 * NW,
+          &nb, reinterpret_cast<const void *>(&ols_mixed4096_kernel<H, PF, NT, NW, OCC>), 64 * NW,
           0) != hipSuccess)
     return 0;
   return nb;
 }
 
-template <class H, bool PF = false, bool NT = true, int NW = 8>
+template <class H, bool PF = false, bool NT = true, int NW = 8, int OCC = (NW == 8 ? 4 : 3)>
 static OlsVariant make_mixed(const char *name, int precision) {
   OlsVariant v{};
   v.name = name;
@@ -491,19 +478,22 @@ static OlsVariant make_mixed(const char *name, int precision) {
   v.lay.R[0] = v.lay.R[1] = v.lay.R[2] = 16;
   for (int i = 3; i < kMaxStages; ++i) v.lay.R[i] = 1;
   v.lds_bytes = 0;
-  v.launch = &launch_mixed4096<H, PF, NT, NW>;
-  v.launch_batch = &launch_mixed4096_batch<H, PF, NT, NW>;
-  v.batch_blocks_per_cu = &mixed_batch_blocks_per_cu<H, PF, NT, NW>;
-  v.grid_blocks_per_cu = &mixed_grid_blocks_per_cu<H, PF, NT, NW>;
+  v.launch = &launch_mixed4096<H, PF, NT, NW, OCC>;
+  v.launch_batch = &launch_mixed4096_batch<H, PF, NT, NW, OCC>;
+  v.batch_blocks_per_cu = &mixed_batch_blocks_per_cu<H, PF, NT, NW, OCC>;
+  v.grid_blocks_per_cu = &mixed_grid_blocks_per_cu<H, PF, NT, NW, OCC>;
   return v;
 }
 
 static const OlsVariant kMixedVariants[] = {
-    make_mixed<_Float16>("fp16_L4096_mfma_w8", 1),
     make_mixed<_Float16, false, true, 4>("fp16_L4096_mfma_w4", 1),
+    make_mixed<_Float16>("fp16_L4096_mfma_w8", 1),
     make_mixed<_Float16, true, true>("fp16_L4096_mfma_w8_pf", 1),
-    make_mixed<_Float16, false, false>("fp16_L4096_mfma_w8_ts", 1),
+    make_mixed<_Float16, true, true, 4, 2>("fp16_L4096_mfma_w4_pf", 1),
+    make_mixed<_Float16, false, true, 8, 6>("fp16_L4096_mfma_w8_o6", 1),
+    make_mixed<_Float16, false, false, 4>("fp16_L4096_mfma_w4_ts", 1),
     make_mixed<__bf16>("bf16_L4096_mfma_w8", 2),
+    make_mixed<__bf16, false, true, 4>("bf16_L4096_mfma_w4", 2),
 };
 
 const OlsVariant *mixed_variants(int *count) {
@@ -512,12 +502,20 @@ const OlsVariant *mixed_variants(int *count) {
 }
 
 // ---- plan-time: 16-bit planar bank in the X layout ------------------------
-// bank[i][plane][row*16 + k2] with row = 16 k0 + k1 for frequency
-// k = k0 + 16 k1 + 256 k2; value conj(FFT_L(h_i))[k] (no 1/L; the kernel
-// removes the factor 2^bank_log2 = L from the power).
+// bank[i][plane][row*16 + slot] with row = 16 k0 + k1 for frequency
+// k = k0 + 16 k1 + 256 k2 and slot = k2, its two 4-value halves swapped
+// when bit 7 of the row is set (the order in which the kernel reads X);
+// value conj(FFT_L(h_i))[k] (no 1/L; the kernel removes the factor
+// 2^bank_log2 = L from the power).
 struct c64m {
   double x, y;
 };
+
+__device__ __forceinline__ int bank_slot_k(int slot) {
+  const int row = slot >> 4;
+  const int k2 = (slot & 15) ^ (((row >> 7) & 1) << 2);
+  return (row >> 4) + 16 * (row & 15) + 256 * k2;
+}
 
 template <class H>
 __global__ void bank_mixed_kernel(H *__restrict__ bank, const c64m *__restrict__ h, int nz, int m,
@@ -525,9 +523,8 @@ __global__ void bank_mixed_kernel(H *__restrict__ bank, const c64m *__restrict__
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (long)nz * L) return;
   const int i = (int)(idx / L);
-  const int slot = (int)(idx % L);  // row*16 + k2
-  const int row = slot >> 4, k2 = slot & 15;
-  const int k = (row >> 4) + 16 * (row & 15) + 256 * k2;
+  const int slot = (int)(idx % L);
+  const int k = bank_slot_k(slot);
   const c64m *hi = h + (long)i * (m + 1);
   double sr = 0.0, si = 0.0;
   for (int j = 0; j <= m; ++j) {
@@ -553,45 +550,33 @@ __global__ void bank_mixed_natural_kernel(c32 *__restrict__ dst, const H *__rest
   if (idx >= (long)nz * L) return;
   const int i = (int)(idx / L);
   const int slot = (int)(idx % L);
-  const int row = slot >> 4, k2 = slot & 15;
-  const int k = (row >> 4) + 16 * (row & 15) + 256 * k2;
+  const int k = bank_slot_k(slot);
   const H *row_i = bank + (long)i * 3 * L;
   const float inv = 1.0f / (float)L;
   dst[(long)i * L + k] = {(float)row_i[slot] * inv, (float)row_i[L + slot] * inv};
 }
 
-// Per-lane constants of the mixed kernel, generated in FP64.
+// Per-lane B operands of the mixed kernel, generated in FP64 (layout at
+// kConstBytes). Lane l holds column c = l & 15 and K rows 8 (l >> 4) + j
+// (j ^ 4 for tiles 8..15, the order of their operand chunks in LDS);
+// K < 16 are real inputs, K >= 16 imaginary inputs, so B1 = [Re M | -Im M]
+// gives the real and B2 = [Im M | Re M] the imaginary part of M x.
 template <class H>
 __global__ void mixed_consts_kernel(unsigned char *__restrict__ out) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= 2 * 16 * 64) return;
   const double kTwoPi = 6.283185307179586476925;
-  if (idx < 17 * 64) {
-    const int mat = idx / 64, lane = idx % 64;
-    const int phase = mat == 0 ? 0 : mat - 1;
-    const int c = lane & 15, kg = lane >> 4;
-    H *b = reinterpret_cast<H *>(out) + (size_t)idx * 16;
-    for (int j = 0; j < 8; ++j) {
-      const int kk = kg * 8 + j, k = kk & 15;
-      double sn, cs;
-      sincos(kTwoPi * (double)((k * (16 * c + phase)) & 255) / 256.0, &sn, &cs);
-      b[j] = (H)(kk < 16 ? cs : -sn);      // B1 = [Re M | -Im M]
-      b[8 + j] = (H)(kk < 16 ? sn : cs);   // B2 = [Im M | Re M]
-    }
-  }
-  c32 *tw = reinterpret_cast<c32 *>(out + kConstB);
-  if (idx < 64 * 4) {
-    const int lane = idx / 4, i = idx % 4;
-    const int g = lane >> 4, c = lane & 15;
+  const int fam = idx / 1024, tile = (idx / 64) % 16, lane = idx % 64;
+  const int c = lane & 15, kg = lane >> 4;
+  H *b = reinterpret_cast<H *>(out) + (size_t)idx * 16;
+  for (int j = 0; j < 8; ++j) {
+    const int kk = kg * 8 + (j ^ (((tile >> 3) & 1) << 2)), k = kk & 15;
+    // Q_t: w4096^(c (256 k + t)); P_p: w256^(k (16 c + p)) = w4096^(16 k (16 c + p))
+    const int e = fam == 0 ? (c * (256 * k + tile)) & 4095 : (16 * k * (16 * c + tile)) & 4095;
     double sn, cs;
-    sincos(kTwoPi * (double)(((4 * g + i) * c) & 255) / 256.0, &sn, &cs);
-    tw[idx] = {(float)cs, (float)sn};
-  }
-  if (idx < 16 * 64 * 4) {
-    const int tile = idx / 256, lane = (idx / 4) % 64, i = idx % 4;
-    const int g = lane >> 4;
-    double sn, cs;
-    sincos(kTwoPi * (double)(((4 * g + i) * tile) & 4095) / 4096.0, &sn, &cs);
-    tw[256 + idx] = {(float)cs, (float)sn};
+    sincos(kTwoPi * (double)e / 4096.0, &sn, &cs);
+    b[j] = (H)(kk < 16 ? cs : -sn);
+    b[8 + j] = (H)(kk < 16 ? sn : cs);
   }
 }
 
@@ -600,10 +585,10 @@ size_t mixed_consts_bytes(int L) { return L == 4096 ? (size_t)kConstBytes : 0; }
 hipError_t launch_mixed_consts(void *out, int L, int precision, hipStream_t s) {
   if (L != 4096) return hipErrorInvalidValue;
   if (precision == 2)
-    hipLaunchKernelGGL(mixed_consts_kernel<__bf16>, dim3(16), dim3(256), 0, s,
+    hipLaunchKernelGGL(mixed_consts_kernel<__bf16>, dim3(8), dim3(256), 0, s,
                        static_cast<unsigned char *>(out));
   else
-    hipLaunchKernelGGL(mixed_consts_kernel<_Float16>, dim3(16), dim3(256), 0, s,
+    hipLaunchKernelGGL(mixed_consts_kernel<_Float16>, dim3(8), dim3(256), 0, s,
                        static_cast<unsigned char *>(out));
   return hipGetLastError();
 }
