@@ -1,22 +1,25 @@
 // Mixed-precision overlap-and-save correlation kernel for gfx950: 16-bit
 // storage (FP16 or BF16), the inverse-FFT stages run as 16 x 16 complex DFT
 // matrices on the matrix cores (v_mfma_f32_16x16x32_{f16,bf16}) with FP32
-// accumulation, twiddles and |.|^2 in FP32.
+// accumulation, |.|^2 in FP32.
 //
-// Segment length L = 4096 = 16^3. Per segment (one block of four waves):
+// Segment length L = 4096 = 16^3. One block of NW waves (TPW = 16 / NW tiles
+// per wave and stage) takes one segment and a group of templates:
 //   forward FFT in FP32 (radix 16, registers + LDS, as in the FP32 kernel),
 //   per-segment power-of-two scale so the largest component is in [4, 8),
-//   X stored once in LDS as two 16-bit planes (re, im);
+//   X rounded to 16 bits and kept in registers (the lanes' operand chunks);
 //   per template: Y = X * T' (packed 16-bit arithmetic; T' = L * T, the
-//   bank without the 1/L, stored as 16-bit planes), then three inverse
-//   radix-16 stages (decimation in time, natural-order output).
+//   bank without the 1/L, stored as 16-bit planes), three inverse radix-16
+//   stages (decimation in time, natural-order output) exchanging through
+//   LDS, |.|^2 staged in LDS and stored one template later as contiguous
+//   1 KB pieces.
 // Each stage processes tiles of 16 butterflies. A tile is one MFMA pair
 // D = A * B: A holds the butterflies as rows and the 16 input values as K
 // (8 real | 8 real | 8 imaginary | 8 imaginary per lane group), B is the DFT
 // matrix in real form ([Re F | -Im F] and [Im F | Re F]), D gives each lane
 // four consecutive rows of one output column. Rows of stage s are chosen as
 // the digit that stage s+1 transforms, so a lane's four outputs are four
-// consecutive inputs of the next stage and go to LDS as one 8-byte write.
+// consecutive inputs of the next stage and go to LDS as 8-byte writes.
 //
 // With digits k = k0 + 16 k1 + 256 k2 (frequency) and n = 256 n0 + 16 n1 + n2
 // (output), the inverse DFT (eq. 3 with the opposite sign, unnormalised) is
@@ -125,16 +128,6 @@ __device__ __forceinline__ typename Vec<H>::v8 load8(const H *plane, int row, in
   return *reinterpret_cast<const typename Vec<H>::v8 *>(plane + lds_chunk(row, h));
 }
 
-// Lanes c and c ^ 8 of each 16-lane row exchange one float: lanes in the
-// 4-lane banks selected by `bank_mask` take the partner's `src`, the others
-// keep `keep` (DPP row rotate by 8).
-template <int BANK_MASK>
-__device__ __forceinline__ float swap8(float keep, float src) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, keep),
-                                                               __builtin_bit_cast(int, src),
-                                                               0x128, 0xf, BANK_MASK, false));
-}
-
 // forward FFT geometry: 4096 = 16 * 16 * 16 over 256 threads (as the FP32 kernel)
 constexpr int kT = 256;
 
@@ -147,8 +140,10 @@ __device__ __forceinline__ int fwd_addr(int t, int n) {
 __device__ __forceinline__ int fpad(int a) { return a + (a >> 4); }
 
 constexpr int kMixF32 = (4096 + 4096 / 16) * 8;
-constexpr int kMix16 = 2 * 2 * kPlane * 2;  // stage buffers Ea, Eb (X is staged in Eb)
-constexpr int kMixSmem = kMixF32 > kMix16 ? kMixF32 : kMix16;
+constexpr int kMix16 = 2 * 2 * kPlane * 2;  // stage buffers Ea, Eb (the forward buffer aliases them)
+// Output staging: 16 blocks of 256 powers, each padded by 16 bytes.
+constexpr int kStageF = 16 * 260;
+constexpr int kMixSmem = (kMixF32 > kMix16 ? kMixF32 : kMix16) + kStageF * 4;
 
 // Per-lane constants, loaded once per block from the plan-time table: the B
 // operands of the wave's TPW tiles in each family.
@@ -189,11 +184,11 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
   typedef typename Vec<H>::v8 v8;
   constexpr int L = 4096;
   constexpr int TPW = 16 / NW;
-  static_assert(TPW % 2 == 0, "output lines are formed from pairs of stage-0' tiles");
   c32 *fbuf = reinterpret_cast<c32 *>(smem);
   H *Ea = reinterpret_cast<H *>(smem);
   H *Eb = Ea + 2 * kPlane;
   H *Xp = Eb;  // X passes through Eb once; first overwritten by stage 1' of the first template
+  float *stg = reinterpret_cast<float *>(smem + (kMixF32 > kMix16 ? kMixF32 : kMix16));
   const int t = threadIdx.x;
   const int lane = t & 63, w = t >> 6;
   const int g = lane >> 4, c = lane & 15, h = g & 1;
@@ -293,17 +288,39 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
     }
   };
 
-  // Output addressing. Stage 0' gives lane (g, c) of tile n1 = TPW w + j the
-  // powers y[256 c + 16 n1 + 4 g + i], i < 4. Tiles 2p and 2p + 1 together
-  // cover 32 consecutive outputs (one 128-byte line) per column c; lanes c
-  // and c ^ 8 exchange one tile's values so that each store instruction
-  // writes eight whole lines: instruction 0 columns 0..7, instruction 1
-  // columns 8..15.
-  const bool lo8 = c < 8;
-  int o_st[2];
-  o_st[0] = 256 * (lo8 ? c : c - 8) + 16 * TPW * w + 16 * (lo8 ? 0 : 1) + 4 * g;
-  o_st[1] = 256 * (lo8 ? c + 8 : c) + 16 * TPW * w + 16 * (lo8 ? 0 : 1) + 4 * g;
+  // Output staging. Stage 0' gives lane (g, c) of tile n1 the powers
+  // y[256 c + 16 n1 + 4 g + i], i < 4; they are staged at float
+  // 260 c + 16 n1 + 4 g (conflict-free 16-byte writes), and after the next
+  // barrier wave w stores outputs [256 TPW w, 256 TPW (w + 1)) of the
+  // segment, 1 KB contiguous per store instruction.
+  auto store_staged = [&](int izr) {
+    if (!active) return;
+    float *prow = power + (int64_t)(izr - row_base) * ld;
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+      const int blk = TPW * w + q;  // 256-output block of the segment
+      const int o0 = 256 * blk + 4 * lane;
+      const f4 v = *reinterpret_cast<const f4 *>(stg + 260 * blk + 4 * lane);
+      const int64_t r0 = (int64_t)s * U + o0 - half;
+      if (o0 >= half && o0 + 3 < half + U && r0 + 3 < nbins &&
+          ((reinterpret_cast<uintptr_t>(prow + r0) & 15) == 0)) {
+        if constexpr (NT) __builtin_nontemporal_store(v, reinterpret_cast<f4 *>(prow + r0));
+        else *reinterpret_cast<f4 *>(prow + r0) = v;
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int o = o0 + i;
+          if (o >= half && o < half + U && r0 + i < nbins) prow[r0 + i] = v[i];
+        }
+      }
+    }
+  };
 
+  // Per template: product + stage 2' | barrier | stage 1', stores of the
+  // previous template's staged powers | barrier | stage 0' into the staging
+  // buffer. With PF the next bank row is loaded after those stores, so the
+  // wait for it (vector loads and stores share one counter) comes a full
+  // phase after both were issued.
   if (PF && z0 < z1) load_bank(z0);
   for (int iz = z0; iz < z1; ++iz) {
     if (!PF) load_bank(iz);
@@ -311,7 +328,6 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
     v8 av[TPW];
 #pragma unroll
     for (int j = 0; j < TPW; ++j) av[j] = xr[j] * btr[j] + xi[j] * bti[j];
-    if (PF && iz + 1 < z1) load_bank(iz + 1);
 #pragma unroll
     for (int j = 0; j < TPW; ++j) {
       const int k0 = TPW * w + j;
@@ -333,48 +349,26 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
       // lane holds rows k0 = 4g + i, column n1 = c
       store_stage<H>(Eb, 16 * c + n2, g, dr, di);  // stage 0' butterfly (n1 = c, n2)
     }
+    if (iz > z0) store_staged(iz - 1);
+    if (PF && iz + 1 < z1) load_bank(iz + 1);
     __syncthreads();
-    // ---- stage 0' (tiles n1 = TPW w + j; rows n2 = c) + |.|^2 + store --------
-    float *prow = power + (int64_t)(iz - row_base) * ld;
+    // ---- stage 0' (tiles n1 = TPW w + j; rows n2 = c) + |.|^2 -> staging ----
 #pragma unroll
-    for (int p = 0; p < TPW / 2; ++p) {
-      f4 pw[2];
+    for (int j = 0; j < TPW; ++j) {
+      const int n1 = TPW * w + j;
+      const v8 a = load8<H>(Eb + (g >> 1) * kPlane, 16 * n1 + c, h);
+      const f4 zero = {0.f, 0.f, 0.f, 0.f};
+      const f4 dr = Vec<H>::mfma(a, K.p1[j], zero);
+      const f4 di = Vec<H>::mfma(a, K.p2[j], zero);
+      f4 pw;
 #pragma unroll
-      for (int jj = 0; jj < 2; ++jj) {
-        const int j = 2 * p + jj;
-        const int n1 = TPW * w + j;
-        const v8 a = load8<H>(Eb + (g >> 1) * kPlane, 16 * n1 + c, h);
-        const f4 zero = {0.f, 0.f, 0.f, 0.f};
-        const f4 dr = Vec<H>::mfma(a, K.p1[j], zero);
-        const f4 di = Vec<H>::mfma(a, K.p2[j], zero);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) pw[jj][i] = (dr[i] * dr[i] + di[i] * di[i]) * pscale;
-      }
-      f4 st[2];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        st[0][i] = swap8<0xc>(pw[0][i], pw[1][i]);  // lanes c >= 8 take tile 2p+1 of c - 8
-        st[1][i] = swap8<0x3>(pw[1][i], pw[0][i]);  // lanes c < 8 take tile 2p of c + 8
-      }
-      if (active) {
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-          const int o0 = o_st[q] + 32 * p;
-          const int64_t r0 = (int64_t)s * U + o0 - half;
-          if (o0 >= half && o0 + 3 < half + U && r0 + 3 < nbins &&
-              ((reinterpret_cast<uintptr_t>(prow + r0) & 15) == 0)) {
-            if constexpr (NT) __builtin_nontemporal_store(st[q], reinterpret_cast<f4 *>(prow + r0));
-            else *reinterpret_cast<f4 *>(prow + r0) = st[q];
-          } else {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              const int o = o0 + i;
-              if (o >= half && o < half + U && r0 + i < nbins) prow[r0 + i] = st[q][i];
-            }
-          }
-        }
-      }
+      for (int i = 0; i < 4; ++i) pw[i] = (dr[i] * dr[i] + di[i] * di[i]) * pscale;
+      *reinterpret_cast<f4 *>(stg + 260 * c + 16 * n1 + 4 * g) = pw;
     }
+  }
+  if (z0 < z1) {
+    __syncthreads();
+    store_staged(z1 - 1);
   }
 }
 
@@ -462,7 +456,7 @@ static int mixed_grid_blocks_per_cu() {
   return nb;
 }
 
-template <class H, bool PF = false, bool NT = true, int NW = 8, int OCC = (NW == 8 ? 4 : 3)>
+template <class H, bool PF, bool NT, int NW, int OCC>
 static OlsVariant make_mixed(const char *name, int precision) {
   OlsVariant v{};
   v.name = name;
@@ -486,14 +480,13 @@ static OlsVariant make_mixed(const char *name, int precision) {
 }
 
 static const OlsVariant kMixedVariants[] = {
-    make_mixed<_Float16, false, true, 4>("fp16_L4096_mfma_w4", 1),
-    make_mixed<_Float16>("fp16_L4096_mfma_w8", 1),
-    make_mixed<_Float16, true, true>("fp16_L4096_mfma_w8_pf", 1),
-    make_mixed<_Float16, true, true, 4, 2>("fp16_L4096_mfma_w4_pf", 1),
-    make_mixed<_Float16, false, true, 8, 6>("fp16_L4096_mfma_w8_o6", 1),
-    make_mixed<_Float16, false, false, 4>("fp16_L4096_mfma_w4_ts", 1),
-    make_mixed<__bf16>("bf16_L4096_mfma_w8", 2),
-    make_mixed<__bf16, false, true, 4>("bf16_L4096_mfma_w4", 2),
+    make_mixed<_Float16, true, true, 16, 8>("fp16_L4096_mfma_w16_pf", 1),
+    make_mixed<_Float16, false, true, 16, 8>("fp16_L4096_mfma_w16", 1),
+    make_mixed<_Float16, true, true, 8, 4>("fp16_L4096_mfma_w8_pf", 1),
+    make_mixed<_Float16, false, true, 8, 4>("fp16_L4096_mfma_w8", 1),
+    make_mixed<_Float16, true, false, 16, 8>("fp16_L4096_mfma_w16_pf_ts", 1),
+    make_mixed<__bf16, true, true, 8, 4>("bf16_L4096_mfma_w8_pf", 2),
+    make_mixed<__bf16, true, true, 16, 8>("bf16_L4096_mfma_w16_pf", 2),
 };
 
 const OlsVariant *mixed_variants(int *count) {
