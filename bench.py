@@ -40,7 +40,9 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=200,
+                    help="untimed steps first (the GPU clock needs tens of ms of load "
+                         "to reach its steady state)")
     ap.add_argument("--workload", default="fp32-paper")
     ap.add_argument("--variant", default=None, help="force a compiled kernel variant")
     ap.add_argument("--zpb", type=int, default=None, help="templates per work unit")
@@ -143,7 +145,10 @@ def run_batch(name, prec, seg_len, nseries, steps, warmup, wave_bytes):
     plan = fdas.Plan(w.zmax, w.dz, w.m, seg_len, prec, device=0)
     info = plan.info
     rows = [int(round(2 * sp.zmax / w.dz)) + 1 for sp in specs]
-    sizes = [r * sp.nbins * 4 for r, sp in zip(rows, specs)]
+    # plane rows padded to 256-byte multiples (ld >= nbins), so that every row
+    # starts on a cache-line boundary
+    lds = [(sp.nbins + 63) // 64 * 64 for sp in specs]
+    sizes = [r * ld * 4 for r, ld in zip(rows, lds)]
     # waves: consecutive series whose planes fit the budget
     waves, cur, acc = [], [], 0
     for i, b in enumerate(sizes):
@@ -160,8 +165,9 @@ def run_batch(name, prec, seg_len, nseries, steps, warmup, wave_bytes):
     for wv in waves:
         outs, off = [], 0
         for i in wv:
-            outs.append(buf[off:off + rows[i] * specs[i].nbins].view(rows[i], specs[i].nbins))
-            off += rows[i] * specs[i].nbins
+            plane = buf[off:off + rows[i] * lds[i]].view(rows[i], lds[i])
+            outs.append(plane[:, :specs[i].nbins])
+            off += rows[i] * lds[i]
         calls.append(([spec_dev[i] for i in wv], [specs[i].zmax for i in wv], outs))
 
     def step():
@@ -239,10 +245,11 @@ def main():
                 "templates_per_block": info.templates_per_block,
                 "plan_ms": round(info.plan_ms, 3), "wall_s_timed": round(r["wall"], 4)})
     traffic = traffic_from_profiles(info.kernel, args.workload)
-    label = ("plain FP32" if prec == "fp32"
-             else f"{prec} storage, MFMA DFT stages, FP32 accumulation")
+    cfg["arithmetic"] = ("plain FP32" if prec == "fp32"
+                         else f"{prec} storage, MFMA DFT stages, FP32 accumulation")
     line = {
-        "metric": f"z-r plane points/s ({label}); % of HBM roofline",
+        "metric": "z\u2013r plane points/s, batched mixed-precision vs plain FP32; "
+                  "% of HBM roofline",
         "value": r["value"],
         "unit": "points/s",
         "n_gpus": 1,

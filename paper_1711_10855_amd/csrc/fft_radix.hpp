@@ -254,6 +254,25 @@ __device__ __forceinline__ T *opaque_ptr(T *p) {
   return p;
 }
 
+// Global-memory view of a pointer. Pointers read from memory (descriptor
+// tables) or passed through asm are generic to the compiler, which then emits
+// FLAT loads and stores; those also count on the LDS counter, so every LDS
+// wait would wait for them too. Through a global pointer the compiler emits
+// global_load / global_store.
+template <class T>
+using gptr = __attribute__((address_space(1))) T *;
+template <class T>
+__device__ __forceinline__ gptr<T> to_global(T *p) {
+  return (gptr<T>)p;
+}
+
+typedef float f2v __attribute__((ext_vector_type(2)));
+// one 8-byte global load of a complex value
+__device__ __forceinline__ c32 ldg(gptr<const c32> p) {
+  const f2v v = *reinterpret_cast<gptr<const f2v>>(p);
+  return {v.x, v.y};
+}
+
 template <int DIR, int R>
 __device__ __forceinline__ void dft(c32 *v) {
   static_assert(R == 2 || R == 4 || R == 8 || R == 16, "radix");

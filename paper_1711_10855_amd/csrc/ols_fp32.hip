@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstdlib>
 #include <type_traits>
 
 #include "fft_radix.hpp"
@@ -151,11 +152,15 @@ __device__ __forceinline__ void exchange(c32 (&d)[Gm::E], c32 *buf0, c32 *buf1, 
 // One work unit: segment s of a spectrum, bank rows [z0, z1), plane rows
 // (iz - row_base). `cur` carries the LDS buffer parity across units.
 template <class Gm, bool TWREG, bool PF>
-__device__ __forceinline__ void ols_unit(const c32 *__restrict__ spec, int64_t nbins,
-                                         const c32 *__restrict__ bank, const c32 *__restrict__ tw,
-                                         float *__restrict__ power, int64_t ld, int s, bool active,
+__device__ __forceinline__ void ols_unit(const c32 *__restrict__ spec_, int64_t nbins,
+                                         const c32 *__restrict__ bank_, const c32 *__restrict__ tw_,
+                                         float *__restrict__ power_, int64_t ld, int s, bool active,
                                          int U, int half, int z0, int z1, int row_base, c32 *buf0,
                                          c32 *buf1, int &cur, int t) {
+  const auto spec = to_global(spec_);
+  const auto bank = to_global(bank_);
+  const auto tw = to_global(tw_);
+  const auto power = to_global(power_);
   constexpr int L = Gm::L, T = Gm::T, E = Gm::E, P = Gm::P;
   const int64_t seg0 = (int64_t)s * U - half;
 
@@ -169,15 +174,15 @@ __device__ __forceinline__ void ols_unit(const c32 *__restrict__ spec, int64_t n
       for (int n = 0; n < R0; ++n) {
         const int64_t g = seg0 + n * S0 + t + j * T;
         c32 v = {0.f, 0.f};
-        if (active && g >= 0 && g < nbins) v = spec[g];
+        if (active && g >= 0 && g < nbins) v = ldg(spec + g);
         x[j * R0 + n] = v;
       }
   }
   c32 bnext[PF ? E : 1];
   if constexpr (PF) {
-    const c32 *brow = bank + (int64_t)z0 * L + t;
+    const auto brow = bank + (int64_t)z0 * L + t;
 #pragma unroll
-    for (int e = 0; e < E; ++e) bnext[e] = brow[e * T];
+    for (int e = 0; e < E; ++e) bnext[e] = ldg(brow + e * T);
   }
 
   // forward, decimation in frequency
@@ -192,7 +197,7 @@ __device__ __forceinline__ void ols_unit(const c32 *__restrict__ spec, int64_t n
         constexpr int N = R * Gm::S(I);
         const int mi = stage_suffix<Gm, I>(t, j);
 #pragma unroll
-        for (int k = 1; k < R; ++k) x[j * R + k] = cmul(x[j * R + k], tw[(k * mi) * (L / N)]);
+        for (int k = 1; k < R; ++k) x[j * R + k] = cmul(x[j * R + k], ldg(tw + (k * mi) * (L / N)));
       }
     }
   });
@@ -209,7 +214,7 @@ __device__ __forceinline__ void ols_unit(const c32 *__restrict__ spec, int64_t n
         const int mi = stage_suffix<Gm, I>(t, j);
 #pragma unroll
         for (int k = 1; k < R; ++k)
-          itw[Gm::TWOFF(I) + j * (R - 1) + k - 1] = tw[(k * mi) * (L / N)];
+          itw[Gm::TWOFF(I) + j * (R - 1) + k - 1] = ldg(tw + (k * mi) * (L / N));
       }
     });
   }
@@ -220,14 +225,14 @@ __device__ __forceinline__ void ols_unit(const c32 *__restrict__ spec, int64_t n
 #pragma unroll
       for (int e = 0; e < E; ++e) y[e] = cmul(x[e], bnext[e]);
       if (iz + 1 < z1) {
-        const c32 *brow = bank + (int64_t)(iz + 1) * L + t;
+        const auto brow = bank + (int64_t)(iz + 1) * L + t;
 #pragma unroll
-        for (int e = 0; e < E; ++e) bnext[e] = brow[e * T];
+        for (int e = 0; e < E; ++e) bnext[e] = ldg(brow + e * T);
       }
     } else {
-      const c32 *brow = bank + (int64_t)iz * L + t;
+      const auto brow = bank + (int64_t)iz * L + t;
 #pragma unroll
-      for (int e = 0; e < E; ++e) y[e] = cmul(x[e], brow[e * T]);
+      for (int e = 0; e < E; ++e) y[e] = cmul(x[e], ldg(brow + e * T));
     }
 
     // inverse, decimation in time: stages P-1 .. 0
@@ -243,7 +248,7 @@ __device__ __forceinline__ void ols_unit(const c32 *__restrict__ spec, int64_t n
           c32 w[R];
 #pragma unroll
           for (int k = 1; k < R; ++k)
-            w[k] = TWREG ? itw[Gm::TWOFF(I) + j * (R - 1) + k - 1] : tw[(k * mi) * (L / N)];
+            w[k] = TWREG ? itw[Gm::TWOFF(I) + j * (R - 1) + k - 1] : ldg(tw + (k * mi) * (L / N));
           dft_tw<+1, true, R>(&y[j * R], w);  // conj twiddles folded into the butterfly
         }
       } else {
@@ -255,7 +260,7 @@ __device__ __forceinline__ void ols_unit(const c32 *__restrict__ spec, int64_t n
     // outputs: slot j*R0 + n holds index n * S0 + t + j T of the segment
     if (active) {
       constexpr int S0 = Gm::S(0), R0 = Gm::R[0];
-      float *prow = power + (int64_t)(iz - row_base) * ld;
+      const auto prow = power + (int64_t)(iz - row_base) * ld;
 #pragma unroll
       for (int j = 0; j < Gm::B(0); ++j)
 #pragma unroll
@@ -328,15 +333,55 @@ __global__ void __launch_bounds__(Gm::T *G) __attribute__((amdgpu_waves_per_eu(W
     const int zg = (int)(local / nsb);
     const int sb = (int)(local % nsb);
     const int s = sb * G + sg;
-    const int z0 = d.row_off + zg * zpb;
-    const int z1 = min(d.row_off + d.nz, z0 + zpb);
+    const int z0 = d.row_off + zg * d.zpb;
+    const int z1 = min(d.row_off + d.nz, z0 + d.zpb);
     ols_unit<Gm, TWREG, PF>(static_cast<const c32 *>(d.spec), d.nbins, opaque_ptr(bank),
                             opaque_ptr(tw), d.power, d.ld, s, s < d.nseg, U, half, z0, z1,
                             d.row_off, lds[0][sg], lds[NB - 1][sg], cur, t);
   }
 }
 
+// Batch as one flat launch: block b takes work item b (same numbering), so
+// the hardware dispatcher hands out items in order as blocks retire. This is
+// the default batch form: on the register-heavy FP32 kernels the persistent
+// loop above measured up to twice as slow per item as this launch.
+template <class Gm, int G, bool TWREG, bool PF, int WPE>
+__global__ void __launch_bounds__(Gm::T *G) __attribute__((amdgpu_waves_per_eu(WPE)))
+    ols_fp32_items_kernel(const SeriesDesc *__restrict__ desc, int nseries,
+                          const c32 *__restrict__ bank, const c32 *__restrict__ tw, int U,
+                          int half, int zpb) {
+  constexpr int T = Gm::T, NB = Gm::NBUF;
+  __shared__ c32 lds[NB][G][Gm::LP];
+  const int tid = threadIdx.x;
+  const int sg = tid / T;
+  const int t = tid % T;
+  const long long item = blockIdx.x;
+  int lo = 0, hi = nseries - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (desc[mid].item_begin <= item) lo = mid;
+    else hi = mid - 1;
+  }
+  const SeriesDesc d = desc[lo];
+  const long long local = item - d.item_begin;
+  const int nsb = (d.nseg + G - 1) / G;
+  const int zg = (int)(local / nsb);
+  const int sb = (int)(local % nsb);
+  const int s = sb * G + sg;
+  const int z0 = d.row_off + zg * d.zpb;
+  const int z1 = min(d.row_off + d.nz, z0 + d.zpb);
+  int cur = 0;
+  ols_unit<Gm, TWREG, PF>(static_cast<const c32 *>(d.spec), d.nbins, bank, tw, d.power, d.ld, s,
+                          s < d.nseg, U, half, z0, z1, d.row_off, lds[0][sg], lds[NB - 1][sg],
+                          cur, t);
+}
+
 __global__ void reset_counter_kernel(unsigned long long *counter) { *counter = 0ULL; }
+
+static bool batch_persistent() {
+  const char *e = std::getenv("FDAS_BATCH_PERSISTENT");
+  return e && *e == '1';
+}
 
 // ---- variant registry ------------------------------------------------------
 
@@ -354,11 +399,19 @@ static hipError_t launch_variant(const OlsArgs &a, hipStream_t st) {
 
 template <class Gm, int G, bool TWREG, bool PF, int WPE>
 static hipError_t launch_batch_variant(const BatchArgs &a, hipStream_t st) {
-  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, st, a.counter);
-  hipLaunchKernelGGL((ols_fp32_batch_kernel<Gm, G, TWREG, PF, WPE>), dim3((unsigned)a.grid),
-                     dim3(Gm::T * G), 0, st, a.desc, a.nseries, a.total, a.counter,
-                     static_cast<const c32 *>(a.bank), static_cast<const c32 *>(a.tw), a.U,
-                     a.half, a.zpb);
+  if (batch_persistent()) {
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, st, a.counter);
+    hipLaunchKernelGGL((ols_fp32_batch_kernel<Gm, G, TWREG, PF, WPE>), dim3((unsigned)a.grid),
+                       dim3(Gm::T * G), 0, st, a.desc, a.nseries, a.total, a.counter,
+                       static_cast<const c32 *>(a.bank), static_cast<const c32 *>(a.tw), a.U,
+                       a.half, a.zpb);
+  } else {
+    if (a.total > (int64_t)0xffffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((ols_fp32_items_kernel<Gm, G, TWREG, PF, WPE>), dim3((unsigned)a.total),
+                       dim3(Gm::T * G), 0, st, a.desc, a.nseries,
+                       static_cast<const c32 *>(a.bank), static_cast<const c32 *>(a.tw), a.U,
+                       a.half, a.zpb);
+  }
   return hipGetLastError();
 }
 

@@ -156,11 +156,11 @@ struct MixedConsts {
 
 template <class H, int NW>
 __device__ __forceinline__ void load_mixed_consts(MixedConsts<H, NW> &K,
-                                                  const unsigned char *__restrict__ consts,
-                                                  int lane, int w) {
+                                                  gptr<const unsigned char> consts, int lane,
+                                                  int w) {
   typedef typename Vec<H>::v8 v8;
   constexpr int TPW = 16 / NW;
-  const v8 *cb = reinterpret_cast<const v8 *>(consts);
+  const gptr<const v8> cb = reinterpret_cast<gptr<const v8>>(consts);
 #pragma unroll
   for (int j = 0; j < TPW; ++j) {
     const int tile = TPW * w + j;
@@ -174,16 +174,21 @@ __device__ __forceinline__ void load_mixed_consts(MixedConsts<H, NW> &K,
 // One work unit of the mixed kernel: segment s, bank rows [z0, z1), plane
 // rows iz - row_base. Every thread of the block calls it (barriers inside).
 template <class H, bool PF, bool NT, int NW>
-__device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ consts,
-                                           const c32 *__restrict__ spec, int64_t nbins,
-                                           const H *__restrict__ bank, const c32 *__restrict__ tw,
-                                           float *__restrict__ power, int64_t ld, int s,
+__device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ consts_,
+                                           const c32 *__restrict__ spec_, int64_t nbins,
+                                           const H *__restrict__ bank_, const c32 *__restrict__ tw_,
+                                           float *__restrict__ power_, int64_t ld, int s,
                                            bool active, int U, int half, int z0, int z1,
                                            int row_base, int bank_log2, unsigned char *smem,
                                            float *s_max) {
   typedef typename Vec<H>::v8 v8;
   constexpr int L = 4096;
   constexpr int TPW = 16 / NW;
+  const auto consts = to_global(consts_);
+  const auto spec = to_global(spec_);
+  const auto bank = to_global(bank_);
+  const auto tw = to_global(tw_);
+  const auto power = to_global(power_);
   c32 *fbuf = reinterpret_cast<c32 *>(smem);
   H *Ea = reinterpret_cast<H *>(smem);
   H *Eb = Ea + 2 * kPlane;
@@ -202,13 +207,13 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
   for (int n = 0; n < 16; ++n) {
     const int64_t gi = seg0 + n * 256 + t;
     c32 v = {0.f, 0.f};
-    if (fw && active && gi >= 0 && gi < nbins) v = spec[gi];
+    if (fw && active && gi >= 0 && gi < nbins) v = ldg(spec + gi);
     x[n] = v;
   }
   if (fw) {
     dft<-1, 16>(x);
 #pragma unroll
-    for (int k = 1; k < 16; ++k) x[k] = cmul(x[k], tw[k * t]);  // W_4096^(k m), m = t < 256
+    for (int k = 1; k < 16; ++k) x[k] = cmul(x[k], ldg(tw + (k * t)));  // W_4096^(k m), m = t < 256
 #pragma unroll
     for (int n = 0; n < 16; ++n) fbuf[fpad(fwd_addr<0>(t, n))] = x[n];
   }
@@ -219,7 +224,7 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
     dft<-1, 16>(x);
     const int mi = t % 16;
 #pragma unroll
-    for (int k = 1; k < 16; ++k) x[k] = cmul(x[k], tw[(k * mi) * 16]);  // W_256^(k m)
+    for (int k = 1; k < 16; ++k) x[k] = cmul(x[k], ldg(tw + (k * mi) * 16));  // W_256^(k m)
   }
   __syncthreads();
   if (fw) {
@@ -279,12 +284,12 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
   const int pu = (g < 2 ? 0 : 1) * L, pv = (g < 2 ? 2 : 0) * L;
   v8 btr[TPW], bti[TPW];
   auto load_bank = [&](int iz) {
-    const H *brow = bank + (int64_t)iz * (3 * L);
+    const auto brow = bank + (int64_t)iz * (3 * L);
 #pragma unroll
     for (int j = 0; j < TPW; ++j) {
       const int row = 16 * (TPW * w + j) + c;
-      btr[j] = *reinterpret_cast<const v8 *>(brow + pu + row * 16 + 8 * h);
-      bti[j] = *reinterpret_cast<const v8 *>(brow + pv + row * 16 + 8 * h);
+      btr[j] = *reinterpret_cast<gptr<const v8>>(brow + pu + row * 16 + 8 * h);
+      bti[j] = *reinterpret_cast<gptr<const v8>>(brow + pv + row * 16 + 8 * h);
     }
   };
 
@@ -295,7 +300,7 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
   // segment, 1 KB contiguous per store instruction.
   auto store_staged = [&](int izr) {
     if (!active) return;
-    float *prow = power + (int64_t)(izr - row_base) * ld;
+    const auto prow = power + (int64_t)(izr - row_base) * ld;
 #pragma unroll
     for (int q = 0; q < TPW; ++q) {
       const int blk = TPW * w + q;  // 256-output block of the segment
@@ -304,8 +309,8 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
       const int64_t r0 = (int64_t)s * U + o0 - half;
       if (o0 >= half && o0 + 3 < half + U && r0 + 3 < nbins &&
           ((reinterpret_cast<uintptr_t>(prow + r0) & 15) == 0)) {
-        if constexpr (NT) __builtin_nontemporal_store(v, reinterpret_cast<f4 *>(prow + r0));
-        else *reinterpret_cast<f4 *>(prow + r0) = v;
+        if constexpr (NT) __builtin_nontemporal_store(v, reinterpret_cast<gptr<f4>>(prow + r0));
+        else *reinterpret_cast<gptr<f4>>(prow + r0) = v;
       } else {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -412,8 +417,8 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(OC
   const long long local = item - d.item_begin;
   const int zg = (int)(local / d.nseg);
   const int sb = (int)(local % d.nseg);
-  const int z0 = d.row_off + zg * zpb;
-  const int z1 = min(d.row_off + d.nz, z0 + zpb);
+  const int z0 = d.row_off + zg * d.zpb;
+  const int z1 = min(d.row_off + d.nz, z0 + d.zpb);
   mixed_unit<H, PF, NT, NW>(consts, static_cast<const c32 *>(d.spec), d.nbins, bank, tw, d.power,
                             d.ld, sb, true, U, half, z0, z1, d.row_off, bank_log2, smem, s_max);
 }

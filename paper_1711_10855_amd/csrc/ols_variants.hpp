@@ -36,7 +36,7 @@ struct SeriesDesc {
   int nseg;             // segments
   int nz;               // rows of this series' plane
   int row_off;          // first bank row used by this series
-  int pad_;
+  int zpb;              // templates per work item of this series
 };
 
 struct BatchArgs {

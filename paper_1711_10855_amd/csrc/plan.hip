@@ -423,7 +423,7 @@ int plan_convolve(fdas_plan_t pl, const void *spec, int64_t nbins, float *power,
 
 // Host side of the batched path: validate and order the series (largest
 // first), lay out their work items, upload the descriptors when the batch
-// changes, and replay one captured graph (counter reset + persistent kernel).
+// changes, and replay one captured graph of the batch launch.
 int plan_convolve_batch(fdas_plan_t pl, const fdas_series *series, int nseries, hipStream_t s) {
   if (!pl->var->launch_batch)
     return set_error(FDAS_ERR_UNSUPPORTED, "kernel %s has no batched form", pl->var->name);
@@ -449,7 +449,9 @@ int plan_convolve_batch(fdas_plan_t pl, const fdas_series *series, int nseries, 
     d.nseg = (int)nseg;
     d.nz = (int)std::nearbyint(span) + 1;
     d.row_off = (int)std::nearbyint(off);
-    d.pad_ = 0;
+    // near-equal template groups of at most the plan's templates per unit
+    const int ng = (d.nz + pl->zpb - 1) / pl->zpb;
+    d.zpb = (d.nz + ng - 1) / ng;
     cost[i] = (double)d.nz * (double)x.nbins;
   }
   std::vector<int> order(nseries);
@@ -461,7 +463,7 @@ int plan_convolve_batch(fdas_plan_t pl, const fdas_series *series, int nseries, 
     sorted[k] = desc[order[k]];
     sorted[k].item_begin = total;
     const int64_t nsb = (sorted[k].nseg + G - 1) / G;
-    const int64_t nzg = (sorted[k].nz + pl->zpb - 1) / pl->zpb;
+    const int64_t nzg = (sorted[k].nz + sorted[k].zpb - 1) / sorted[k].zpb;
     total += nsb * nzg;
   }
   if (total == 0) return FDAS_OK;

@@ -1,5 +1,6 @@
-"""Batched path (one persistent, graph-captured launch over many series of
-uneven length and per-series zmax) against the FP64 oracle, through the C ABI."""
+"""Batched path (one graph-captured launch over many series of uneven length
+and per-series zmax; flat work-item grid by default, persistent work-queue
+loop with FDAS_BATCH_PERSISTENT=1) against the FP64 oracle, through the C ABI."""
 
 import os
 
@@ -37,7 +38,7 @@ SPECS = [(5000, 16.0, 0), (1, 8.0, 0), (191, 0.0, 3), (20000, 16.0, 7), (777, 4.
 
 @pytest.fixture
 def env():
-    saved = {k: os.environ.get(k) for k in ("FDAS_NO_GRAPH",)}
+    saved = {k: os.environ.get(k) for k in ("FDAS_NO_GRAPH", "FDAS_BATCH_PERSISTENT")}
     yield os.environ
     for k, v in saved.items():
         if v is None:
@@ -46,10 +47,12 @@ def env():
             os.environ[k] = v
 
 
-@pytest.mark.parametrize("L,m", [(256, 64), (1024, 128)])
-def test_batch_matches_oracle(gpu, L, m):
+@pytest.mark.parametrize("L,m,persistent", [(256, 64, "0"), (1024, 128, "0"), (256, 64, "1"),
+                                             (1024, 128, "1")])
+def test_batch_matches_oracle(gpu, env, L, m, persistent):
+    env["FDAS_BATCH_PERSISTENT"] = persistent
     spectra, zmaxs, outs = make_batch(16.0, 2.0, SPECS)
-    print(f"batch L={L} m={m} nseries={len(SPECS)}", flush=True)
+    print(f"batch L={L} m={m} nseries={len(SPECS)} persistent={persistent}", flush=True)
     with gpu.Plan(16.0, 2.0, m, L) as p:
         p.convolve_batch([to_dev(a) for a in spectra], zmaxs, outs)
         res = [o.cpu().numpy() for o in outs]
