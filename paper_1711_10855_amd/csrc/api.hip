@@ -60,6 +60,8 @@ int resolve_params(const fdas_params *in, fdas_params *out, int *nz_out) {
   if (p.precision != FDAS_FP32 && p.precision != FDAS_MIXED_FP16 &&
       p.precision != FDAS_MIXED_BF16)
     return set_error(FDAS_ERR_INVALID, "unknown precision %d", p.precision);
+  if ((p.flags & FDAS_FLAG_SPLIT) && p.precision == FDAS_FP32)
+    return set_error(FDAS_ERR_INVALID, "FDAS_FLAG_SPLIT applies to the mixed precisions only");
   if (p.m == 0) {
     p.m = next_pow2(2.0 * p.zmax + 32.0);
     if (p.m < 8) p.m = 8;

@@ -99,15 +99,43 @@ typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // A lane holds four consecutive values (4g .. 4g+3 of row `row` of the next
-// stage) of both planes; each plane's four go out as one 8-byte write.
-template <class H>
+// stage) of both planes; each plane's four go out as one 8-byte write. With
+// SPLIT the buffer has four planes (re hi, im hi, re lo, im lo): each value
+// v is stored as hi = round16(v) and lo = round16(v - hi).
+template <class H, bool SPLIT>
 __device__ __forceinline__ void store_stage(H *buf, int row, int g, const f4 &re,
                                             const f4 &im) {
-  const typename Vec<H>::v4 r4 = {(H)re[0], (H)re[1], (H)re[2], (H)re[3]};
-  const typename Vec<H>::v4 i4 = {(H)im[0], (H)im[1], (H)im[2], (H)im[3]};
+  typedef typename Vec<H>::v4 v4;
+  const v4 rh = {(H)re[0], (H)re[1], (H)re[2], (H)re[3]};
+  const v4 ih = {(H)im[0], (H)im[1], (H)im[2], (H)im[3]};
   const int o = lds_idx(row, 4 * g);
-  *reinterpret_cast<typename Vec<H>::v4 *>(buf + o) = r4;
-  *reinterpret_cast<typename Vec<H>::v4 *>(buf + kPlane + o) = i4;
+  *reinterpret_cast<v4 *>(buf + o) = rh;
+  *reinterpret_cast<v4 *>(buf + kPlane + o) = ih;
+  if constexpr (SPLIT) {
+    v4 rl, il;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      rl[i] = (H)(re[i] - (float)rh[i]);
+      il[i] = (H)(im[i] - (float)ih[i]);
+    }
+    *reinterpret_cast<v4 *>(buf + 2 * kPlane + o) = rl;
+    *reinterpret_cast<v4 *>(buf + 3 * kPlane + o) = il;
+  }
+}
+
+// D = A B with FP32 accumulation; with SPLIT, A = ah + al and B = bh + bl and
+// D = ah bh + ah bl + al bh (the lo x lo term is below the FP32 rounding of
+// the sum).
+template <class H, bool SPLIT>
+__device__ __forceinline__ f4 mma(const typename Vec<H>::v8 &ah, const typename Vec<H>::v8 &al,
+                                  const typename Vec<H>::v8 &bh, const typename Vec<H>::v8 &bl) {
+  const f4 zero = {0.f, 0.f, 0.f, 0.f};
+  f4 d = Vec<H>::mfma(ah, bh, zero);
+  if constexpr (SPLIT) {
+    d = Vec<H>::mfma(ah, bl, d);
+    d = Vec<H>::mfma(al, bh, d);
+  }
+  return d;
 }
 
 // Values e0 .. e0+7 of row `row` (one plane), as two 8-byte groups.
@@ -140,27 +168,42 @@ __device__ __forceinline__ int fwd_addr(int t, int n) {
 __device__ __forceinline__ int fpad(int a) { return a + (a >> 4); }
 
 constexpr int kMixF32 = (4096 + 4096 / 16) * 8;
-constexpr int kMix16 = 2 * 2 * kPlane * 2;  // stage buffers Ea, Eb (the forward buffer aliases them)
+// stage buffers Ea, Eb of 2 (4 with SPLIT) planes; the forward buffer aliases them
+template <bool SPLIT>
+constexpr int mix_stage_bytes() {
+  return 2 * (SPLIT ? 4 : 2) * kPlane * 2 > kMixF32 ? 2 * (SPLIT ? 4 : 2) * kPlane * 2 : kMixF32;
+}
 // Output staging: 16 blocks of 256 powers, each padded by 16 bytes.
 constexpr int kStageF = 16 * 260;
-constexpr int kMixSmem = (kMixF32 > kMix16 ? kMixF32 : kMix16) + kStageF * 4;
+template <bool SPLIT>
+constexpr int mix_smem() {
+  return mix_stage_bytes<SPLIT>() + kStageF * 4;
+}
+// With SPLIT, X goes from the forward FFT to the lanes in FP32: 256 rows of
+// 16 values padded to 17, placed at Eb (first written by stage 1').
+constexpr int kXF32Bytes = 256 * 17 * 8;
+static_assert(2 * kPlane * 2 * 2 + kXF32Bytes <= mix_smem<true>(), "X transfer fits");
 
 // Per-lane constants, loaded once per block from the plan-time table: the B
-// operands of the wave's TPW tiles in each family.
-template <class H, int NW>
+// operands of the wave's TPW tiles in each family (hi parts; with SPLIT also
+// the lo parts, B - round16(B)).
+template <class H, int NW, bool SPLIT>
 struct MixedConsts {
   static constexpr int TPW = 16 / NW;
+  static constexpr int NL = SPLIT ? TPW : 1;
   typename Vec<H>::v8 q1[TPW], q2[TPW];  // stage 2' tiles k0 = TPW w + j
   typename Vec<H>::v8 p1[TPW], p2[TPW];  // stage 1' tiles n2 and stage 0' tiles n1 = TPW w + j
+  typename Vec<H>::v8 q1l[NL], q2l[NL], p1l[NL], p2l[NL];
 };
 
-template <class H, int NW>
-__device__ __forceinline__ void load_mixed_consts(MixedConsts<H, NW> &K,
+template <class H, int NW, bool SPLIT>
+__device__ __forceinline__ void load_mixed_consts(MixedConsts<H, NW, SPLIT> &K,
                                                   gptr<const unsigned char> consts, int lane,
                                                   int w) {
   typedef typename Vec<H>::v8 v8;
   constexpr int TPW = 16 / NW;
   const gptr<const v8> cb = reinterpret_cast<gptr<const v8>>(consts);
+  constexpr int LO = 2 * 16 * 64 * 2;  // v8 entries per part
 #pragma unroll
   for (int j = 0; j < TPW; ++j) {
     const int tile = TPW * w + j;
@@ -168,12 +211,18 @@ __device__ __forceinline__ void load_mixed_consts(MixedConsts<H, NW> &K,
     K.q2[j] = cb[((0 * 16 + tile) * 64 + lane) * 2 + 1];
     K.p1[j] = cb[((1 * 16 + tile) * 64 + lane) * 2];
     K.p2[j] = cb[((1 * 16 + tile) * 64 + lane) * 2 + 1];
+    if constexpr (SPLIT) {
+      K.q1l[j] = cb[LO + ((0 * 16 + tile) * 64 + lane) * 2];
+      K.q2l[j] = cb[LO + ((0 * 16 + tile) * 64 + lane) * 2 + 1];
+      K.p1l[j] = cb[LO + ((1 * 16 + tile) * 64 + lane) * 2];
+      K.p2l[j] = cb[LO + ((1 * 16 + tile) * 64 + lane) * 2 + 1];
+    }
   }
 }
 
 // One work unit of the mixed kernel: segment s, bank rows [z0, z1), plane
 // rows iz - row_base. Every thread of the block calls it (barriers inside).
-template <class H, bool PF, bool NT, int NW>
+template <class H, bool PF, bool NT, int NW, bool SPLIT>
 __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ consts_,
                                            const c32 *__restrict__ spec_, int64_t nbins,
                                            const H *__restrict__ bank_, const c32 *__restrict__ tw_,
@@ -189,11 +238,13 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
   const auto bank = to_global(bank_);
   const auto tw = to_global(tw_);
   const auto power = to_global(power_);
+  constexpr int NP = SPLIT ? 4 : 2;  // planes per stage buffer
   c32 *fbuf = reinterpret_cast<c32 *>(smem);
   H *Ea = reinterpret_cast<H *>(smem);
-  H *Eb = Ea + 2 * kPlane;
+  H *Eb = Ea + NP * kPlane;
   H *Xp = Eb;  // X passes through Eb once; first overwritten by stage 1' of the first template
-  float *stg = reinterpret_cast<float *>(smem + (kMixF32 > kMix16 ? kMixF32 : kMix16));
+  c32 *Xf = reinterpret_cast<c32 *>(Eb);  // (SPLIT) the same, in FP32
+  float *stg = reinterpret_cast<float *>(smem + mix_stage_bytes<SPLIT>());
   const int t = threadIdx.x;
   const int lane = t & 63, w = t >> 6;
   const int g = lane >> 4, c = lane & 15, h = g & 1;
@@ -256,40 +307,62 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
   // power = |y'|^2 * 2^(-2 (a + b)) with a = 3 - ex, b = bank_log2
   const float pscale = ldexpf(1.0f, -2 * (3 - ex + bank_log2));
   if (fw) {
+    if constexpr (SPLIT) {
 #pragma unroll
-    for (int e0 = 0; e0 < 16; e0 += 8) {
-      store8<H>(Xp, t, e0, &x[e0], false, xscale);
-      store8<H>(Xp + kPlane, t, e0, &x[e0], true, xscale);
+      for (int e = 0; e < 16; ++e) Xf[t * 17 + e] = {x[e].x * xscale, x[e].y * xscale};
+    } else {
+#pragma unroll
+      for (int e0 = 0; e0 < 16; e0 += 8) {
+        store8<H>(Xp, t, e0, &x[e0], false, xscale);
+        store8<H>(Xp + kPlane, t, e0, &x[e0], true, xscale);
+      }
     }
   }
   __syncthreads();  // X complete
 
   // The B operands are loaded only now, so that they do not hold registers
   // during the forward FFT.
-  MixedConsts<H, NW> K;
-  load_mixed_consts<H, NW>(K, consts, lane, w);
+  MixedConsts<H, NW, SPLIT> K;
+  load_mixed_consts<H, NW, SPLIT>(K, consts, lane, w);
 
   // X stays in registers for the whole template loop: rows 16 k0 + c of the
-  // wave's tiles k0 = TPW w + j, chunk h, both planes.
-  v8 xr[TPW], xi[TPW];
+  // wave's tiles k0 = TPW w + j, chunk h, both planes (with SPLIT in FP32,
+  // in the order the operand chunks use).
+  v8 xr[SPLIT ? 1 : TPW], xi[SPLIT ? 1 : TPW];
+  float xrf[SPLIT ? TPW : 1][8], xif[SPLIT ? TPW : 1][8];
 #pragma unroll
   for (int j = 0; j < TPW; ++j) {
     const int row = 16 * (TPW * w + j) + c;
-    xr[j] = load8<H>(Xp, row, h);
-    xi[j] = load8<H>(Xp + kPlane, row, h);
+    if constexpr (SPLIT) {
+      const int sw = ((row >> 7) & 1) << 2;  // 4-value halves swapped on rows with bit 7 set
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const c32 v = Xf[row * 17 + 8 * h + (i ^ sw)];
+        xrf[j][i] = v.x;
+        xif[j][i] = v.y;
+      }
+    } else {
+      xr[j] = load8<H>(Xp, row, h);
+      xi[j] = load8<H>(Xp + kPlane, row, h);
+    }
   }
 
   // Bank rows for the same lanes; re lanes (g < 2) compute xr*tr + xi*(-ti),
-  // im lanes xr*ti + xi*tr: plane offsets.
+  // im lanes xr*ti + xi*tr: plane offsets (SPLIT: lo parts 3 planes further).
+  constexpr int BP = SPLIT ? 6 : 3;  // planes per bank row
   const int pu = (g < 2 ? 0 : 1) * L, pv = (g < 2 ? 2 : 0) * L;
-  v8 btr[TPW], bti[TPW];
+  v8 btr[TPW], bti[TPW], btrl[SPLIT ? TPW : 1], btil[SPLIT ? TPW : 1];
   auto load_bank = [&](int iz) {
-    const auto brow = bank + (int64_t)iz * (3 * L);
+    const auto brow = bank + (int64_t)iz * (BP * L);
 #pragma unroll
     for (int j = 0; j < TPW; ++j) {
       const int row = 16 * (TPW * w + j) + c;
       btr[j] = *reinterpret_cast<gptr<const v8>>(brow + pu + row * 16 + 8 * h);
       bti[j] = *reinterpret_cast<gptr<const v8>>(brow + pv + row * 16 + 8 * h);
+      if constexpr (SPLIT) {
+        btrl[j] = *reinterpret_cast<gptr<const v8>>(brow + 3 * L + pu + row * 16 + 8 * h);
+        btil[j] = *reinterpret_cast<gptr<const v8>>(brow + 3 * L + pv + row * 16 + 8 * h);
+      }
     }
   };
 
@@ -330,17 +403,30 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
   for (int iz = z0; iz < z1; ++iz) {
     if (!PF) load_bank(iz);
     // ---- product + stage 2' (tiles k0 = TPW w + j; rows k1 = c; chunk h) ----
-    v8 av[TPW];
+    v8 av[TPW], avl[SPLIT ? TPW : 1];
 #pragma unroll
-    for (int j = 0; j < TPW; ++j) av[j] = xr[j] * btr[j] + xi[j] * bti[j];
+    for (int j = 0; j < TPW; ++j) {
+      if constexpr (SPLIT) {
+        // Y = X T in FP32 from X (FP32) and T = hi + lo, then Y = hi + lo
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const float tr = (float)btr[j][i] + (float)btrl[j][i];
+          const float ti = (float)bti[j][i] + (float)btil[j][i];
+          const float y = __builtin_fmaf(xrf[j][i], tr, xif[j][i] * ti);
+          av[j][i] = (H)y;
+          avl[j][i] = (H)(y - (float)av[j][i]);
+        }
+      } else {
+        av[j] = xr[j] * btr[j] + xi[j] * bti[j];
+      }
+    }
 #pragma unroll
     for (int j = 0; j < TPW; ++j) {
       const int k0 = TPW * w + j;
-      const f4 zero = {0.f, 0.f, 0.f, 0.f};
-      const f4 dr = Vec<H>::mfma(av[j], K.q1[j], zero);
-      const f4 di = Vec<H>::mfma(av[j], K.q2[j], zero);
+      const f4 dr = mma<H, SPLIT>(av[j], avl[SPLIT ? j : 0], K.q1[j], K.q1l[SPLIT ? j : 0]);
+      const f4 di = mma<H, SPLIT>(av[j], avl[SPLIT ? j : 0], K.q2[j], K.q2l[SPLIT ? j : 0]);
       // lane holds rows k1 = 4g + i, column n2 = c
-      store_stage<H>(Ea, 16 * c + k0, g, dr, di);  // stage 1' butterfly (k0, n2 = c)
+      store_stage<H, SPLIT>(Ea, 16 * c + k0, g, dr, di);  // stage 1' butterfly (k0, n2 = c)
     }
     __syncthreads();
     // ---- stage 1' (tiles n2 = TPW w + j; rows k0 = c) -------------------------
@@ -348,11 +434,11 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
     for (int j = 0; j < TPW; ++j) {
       const int n2 = TPW * w + j;
       const v8 a = load8<H>(Ea + (g >> 1) * kPlane, 16 * n2 + c, h);
-      const f4 zero = {0.f, 0.f, 0.f, 0.f};
-      const f4 dr = Vec<H>::mfma(a, K.p1[j], zero);
-      const f4 di = Vec<H>::mfma(a, K.p2[j], zero);
+      const v8 al = SPLIT ? load8<H>(Ea + (2 + (g >> 1)) * kPlane, 16 * n2 + c, h) : a;
+      const f4 dr = mma<H, SPLIT>(a, al, K.p1[j], K.p1l[SPLIT ? j : 0]);
+      const f4 di = mma<H, SPLIT>(a, al, K.p2[j], K.p2l[SPLIT ? j : 0]);
       // lane holds rows k0 = 4g + i, column n1 = c
-      store_stage<H>(Eb, 16 * c + n2, g, dr, di);  // stage 0' butterfly (n1 = c, n2)
+      store_stage<H, SPLIT>(Eb, 16 * c + n2, g, dr, di);  // stage 0' butterfly (n1 = c, n2)
     }
     if (iz > z0) store_staged(iz - 1);
     if (PF && iz + 1 < z1) load_bank(iz + 1);
@@ -362,9 +448,9 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
     for (int j = 0; j < TPW; ++j) {
       const int n1 = TPW * w + j;
       const v8 a = load8<H>(Eb + (g >> 1) * kPlane, 16 * n1 + c, h);
-      const f4 zero = {0.f, 0.f, 0.f, 0.f};
-      const f4 dr = Vec<H>::mfma(a, K.p1[j], zero);
-      const f4 di = Vec<H>::mfma(a, K.p2[j], zero);
+      const v8 al = SPLIT ? load8<H>(Eb + (2 + (g >> 1)) * kPlane, 16 * n1 + c, h) : a;
+      const f4 dr = mma<H, SPLIT>(a, al, K.p1[j], K.p1l[SPLIT ? j : 0]);
+      const f4 di = mma<H, SPLIT>(a, al, K.p2[j], K.p2l[SPLIT ? j : 0]);
       f4 pw;
 #pragma unroll
       for (int i = 0; i < 4; ++i) pw[i] = (dr[i] * dr[i] + di[i] * di[i]) * pscale;
@@ -377,19 +463,19 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
   }
 }
 
-template <class H, bool PF, bool NT, int NW, int OCC>
+template <class H, bool PF, bool NT, int NW, int OCC, bool SPLIT>
 __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(OCC, OCC)))
     ols_mixed4096_kernel(const c32 *__restrict__ spec, int64_t nbins, const H *__restrict__ bank,
                          const c32 *__restrict__ tw, const unsigned char *__restrict__ consts,
                          float *__restrict__ power, int64_t ld, int nseg, int U, int half, int nz,
                          int zpb, int nsb, int bank_log2) {
-  __shared__ __attribute__((aligned(16))) unsigned char smem[kMixSmem];
+  __shared__ __attribute__((aligned(16))) unsigned char smem[mix_smem<SPLIT>()];
   __shared__ float s_max[NW];
   const int sb = blockIdx.x % nsb;
   const int zg = blockIdx.x / nsb;
   const int z0 = zg * zpb;
   const int z1 = min(nz, z0 + zpb);
-  mixed_unit<H, PF, NT, NW>(consts, spec, nbins, bank, tw, power, ld, sb, sb < nseg, U, half, z0, z1,
+  mixed_unit<H, PF, NT, NW, SPLIT>(consts, spec, nbins, bank, tw, power, ld, sb, sb < nseg, U, half, z0, z1,
                             0, bank_log2, smem, s_max);
 }
 
@@ -398,13 +484,13 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(OC
 // dispatcher hands out items in that order as blocks retire. Same body as
 // the single-series kernel; used because the persistent loop around this
 // body does not fit the register budget.
-template <class H, bool PF, bool NT, int NW, int OCC>
+template <class H, bool PF, bool NT, int NW, int OCC, bool SPLIT>
 __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(OCC, OCC)))
     ols_mixed4096_items_kernel(const SeriesDesc *__restrict__ desc, int nseries,
                                const H *__restrict__ bank, const c32 *__restrict__ tw,
                                const unsigned char *__restrict__ consts, int U, int half, int zpb,
                                int bank_log2) {
-  __shared__ __attribute__((aligned(16))) unsigned char smem[kMixSmem];
+  __shared__ __attribute__((aligned(16))) unsigned char smem[mix_smem<SPLIT>()];
   __shared__ float s_max[NW];
   const long long item = blockIdx.x;
   int lo = 0, hi = nseries - 1;
@@ -419,16 +505,16 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(OC
   const int sb = (int)(local % d.nseg);
   const int z0 = d.row_off + zg * d.zpb;
   const int z1 = min(d.row_off + d.nz, z0 + d.zpb);
-  mixed_unit<H, PF, NT, NW>(consts, static_cast<const c32 *>(d.spec), d.nbins, bank, tw, d.power,
+  mixed_unit<H, PF, NT, NW, SPLIT>(consts, static_cast<const c32 *>(d.spec), d.nbins, bank, tw, d.power,
                             d.ld, sb, true, U, half, z0, z1, d.row_off, bank_log2, smem, s_max);
 }
 
-template <class H, bool PF, bool NT, int NW, int OCC>
+template <class H, bool PF, bool NT, int NW, int OCC, bool SPLIT>
 static hipError_t launch_mixed4096(const OlsArgs &a, hipStream_t st) {
   const int nsb = a.nseg;
   const int nzg = (a.nz + a.zpb - 1) / a.zpb;
   const long blocks = (long)nsb * nzg;
-  hipLaunchKernelGGL((ols_mixed4096_kernel<H, PF, NT, NW, OCC>), dim3((unsigned)blocks), dim3(64 * NW), 0, st,
+  hipLaunchKernelGGL((ols_mixed4096_kernel<H, PF, NT, NW, OCC, SPLIT>), dim3((unsigned)blocks), dim3(64 * NW), 0, st,
                      static_cast<const c32 *>(a.spec), a.nbins, static_cast<const H *>(a.bank),
                      static_cast<const c32 *>(a.tw),
                      static_cast<const unsigned char *>(a.consts), a.power, a.ld, a.nseg, a.U,
@@ -436,32 +522,32 @@ static hipError_t launch_mixed4096(const OlsArgs &a, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <class H, bool PF, bool NT, int NW, int OCC>
+template <class H, bool PF, bool NT, int NW, int OCC, bool SPLIT>
 static hipError_t launch_mixed4096_batch(const BatchArgs &a, hipStream_t st) {
   if (a.total > (int64_t)0xffffffffLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((ols_mixed4096_items_kernel<H, PF, NT, NW, OCC>), dim3((unsigned)a.total),
+  hipLaunchKernelGGL((ols_mixed4096_items_kernel<H, PF, NT, NW, OCC, SPLIT>), dim3((unsigned)a.total),
                      dim3(64 * NW), 0, st, a.desc, a.nseries, static_cast<const H *>(a.bank),
                      static_cast<const c32 *>(a.tw), static_cast<const unsigned char *>(a.consts),
                      a.U, a.half, a.zpb, a.bank_log2);
   return hipGetLastError();
 }
 
-template <class H, bool PF, bool NT, int NW, int OCC>
+template <class H, bool PF, bool NT, int NW, int OCC, bool SPLIT>
 static int mixed_batch_blocks_per_cu() {
   return 1;  // flat launch: the grid is the item count
 }
 
-template <class H, bool PF, bool NT, int NW, int OCC>
+template <class H, bool PF, bool NT, int NW, int OCC, bool SPLIT>
 static int mixed_grid_blocks_per_cu() {
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &nb, reinterpret_cast<const void *>(&ols_mixed4096_kernel<H, PF, NT, NW, OCC>), 64 * NW,
+          &nb, reinterpret_cast<const void *>(&ols_mixed4096_kernel<H, PF, NT, NW, OCC, SPLIT>), 64 * NW,
           0) != hipSuccess)
     return 0;
   return nb;
 }
 
-template <class H, bool PF, bool NT, int NW, int OCC>
+template <class H, bool PF, bool NT, int NW, int OCC, bool SPLIT>
 static OlsVariant make_mixed(const char *name, int precision) {
   OlsVariant v{};
   v.name = name;
@@ -470,6 +556,7 @@ static OlsVariant make_mixed(const char *name, int precision) {
   v.G = 1;
   v.nbuf = 1;
   v.precision = precision;
+  v.split = SPLIT ? 1 : 0;
   v.lay.L = 4096;
   v.lay.T = 256;
   v.lay.E = 16;
@@ -477,21 +564,26 @@ static OlsVariant make_mixed(const char *name, int precision) {
   v.lay.R[0] = v.lay.R[1] = v.lay.R[2] = 16;
   for (int i = 3; i < kMaxStages; ++i) v.lay.R[i] = 1;
   v.lds_bytes = 0;
-  v.launch = &launch_mixed4096<H, PF, NT, NW, OCC>;
-  v.launch_batch = &launch_mixed4096_batch<H, PF, NT, NW, OCC>;
-  v.batch_blocks_per_cu = &mixed_batch_blocks_per_cu<H, PF, NT, NW, OCC>;
-  v.grid_blocks_per_cu = &mixed_grid_blocks_per_cu<H, PF, NT, NW, OCC>;
+  v.launch = &launch_mixed4096<H, PF, NT, NW, OCC, SPLIT>;
+  v.launch_batch = &launch_mixed4096_batch<H, PF, NT, NW, OCC, SPLIT>;
+  v.batch_blocks_per_cu = &mixed_batch_blocks_per_cu<H, PF, NT, NW, OCC, SPLIT>;
+  v.grid_blocks_per_cu = &mixed_grid_blocks_per_cu<H, PF, NT, NW, OCC, SPLIT>;
   return v;
 }
 
 static const OlsVariant kMixedVariants[] = {
-    make_mixed<_Float16, true, true, 16, 8>("fp16_L4096_mfma_w16_pf", 1),
-    make_mixed<_Float16, false, true, 16, 8>("fp16_L4096_mfma_w16", 1),
-    make_mixed<_Float16, true, true, 8, 4>("fp16_L4096_mfma_w8_pf", 1),
-    make_mixed<_Float16, false, true, 8, 4>("fp16_L4096_mfma_w8", 1),
-    make_mixed<_Float16, true, false, 16, 8>("fp16_L4096_mfma_w16_pf_ts", 1),
-    make_mixed<__bf16, true, true, 8, 4>("bf16_L4096_mfma_w8_pf", 2),
-    make_mixed<__bf16, true, true, 16, 8>("bf16_L4096_mfma_w16_pf", 2),
+    make_mixed<_Float16, true, true, 16, 8, false>("fp16_L4096_mfma_w16_pf", 1),
+    make_mixed<_Float16, false, true, 16, 8, false>("fp16_L4096_mfma_w16", 1),
+    make_mixed<_Float16, true, true, 8, 4, false>("fp16_L4096_mfma_w8_pf", 1),
+    make_mixed<_Float16, false, true, 8, 4, false>("fp16_L4096_mfma_w8", 1),
+    make_mixed<_Float16, true, false, 16, 8, false>("fp16_L4096_mfma_w16_pf_ts", 1),
+    make_mixed<__bf16, true, true, 8, 4, false>("bf16_L4096_mfma_w8_pf", 2),
+    make_mixed<__bf16, true, true, 16, 8, false>("bf16_L4096_mfma_w16_pf", 2),
+    // hi + lo split products (FDAS_FLAG_SPLIT)
+    make_mixed<_Float16, false, true, 16, 4, true>("fp16_L4096_mfma_split_w16", 1),
+    make_mixed<_Float16, true, true, 16, 4, true>("fp16_L4096_mfma_split_w16_pf", 1),
+    make_mixed<__bf16, false, true, 16, 4, true>("bf16_L4096_mfma_split_w16", 2),
+    make_mixed<__bf16, true, true, 16, 4, true>("bf16_L4096_mfma_split_w16_pf", 2),
 };
 
 const OlsVariant *mixed_variants(int *count) {
@@ -504,7 +596,8 @@ const OlsVariant *mixed_variants(int *count) {
 // k = k0 + 16 k1 + 256 k2 and slot = k2, its two 4-value halves swapped
 // when bit 7 of the row is set (the order in which the kernel reads X);
 // value conj(FFT_L(h_i))[k] (no 1/L; the kernel removes the factor
-// 2^bank_log2 = L from the power).
+// 2^bank_log2 = L from the power). Planes: Re, Im, -Im (rounded to 16 bits);
+// with split, three more planes hold the residuals v - round16(v).
 struct c64m {
   double x, y;
 };
@@ -516,8 +609,15 @@ __device__ __forceinline__ int bank_slot_k(int slot) {
 }
 
 template <class H>
+__device__ __forceinline__ void put_split(H *hi, H *lo, double v) {
+  const H a = (H)v;
+  *hi = a;
+  if (lo) *lo = (H)(v - (double)(float)a);
+}
+
+template <class H>
 __global__ void bank_mixed_kernel(H *__restrict__ bank, const c64m *__restrict__ h, int nz, int m,
-                                  int L) {
+                                  int L, int split) {
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (long)nz * L) return;
   const int i = (int)(idx / L);
@@ -535,85 +635,96 @@ __global__ void bank_mixed_kernel(H *__restrict__ bank, const c64m *__restrict__
     sr += v.x * cs - v.y * sn;
     si += v.x * sn + v.y * cs;
   }
-  H *row_i = bank + (long)i * 3 * L;
-  row_i[slot] = (H)sr;             // Re T'
-  row_i[L + slot] = (H)(-si);      // Im T'
-  row_i[2 * L + slot] = (H)si;     // -Im T'
+  H *row_i = bank + (long)i * (split ? 6 : 3) * L;
+  H *lo = split ? row_i + 3 * L : nullptr;
+  put_split(row_i + slot, lo ? lo + slot : nullptr, sr);                // Re T'
+  put_split(row_i + L + slot, lo ? lo + L + slot : nullptr, -si);       // Im T'
+  put_split(row_i + 2 * L + slot, lo ? lo + 2 * L + slot : nullptr, si);  // -Im T'
 }
 
 template <class H>
 __global__ void bank_mixed_natural_kernel(c32 *__restrict__ dst, const H *__restrict__ bank,
-                                          int nz, int L) {
+                                          int nz, int L, int split) {
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (long)nz * L) return;
   const int i = (int)(idx / L);
   const int slot = (int)(idx % L);
   const int k = bank_slot_k(slot);
-  const H *row_i = bank + (long)i * 3 * L;
+  const H *row_i = bank + (long)i * (split ? 6 : 3) * L;
+  float re = (float)row_i[slot], im = (float)row_i[L + slot];
+  if (split) {
+    re += (float)row_i[3 * L + slot];
+    im += (float)row_i[4 * L + slot];
+  }
   const float inv = 1.0f / (float)L;
-  dst[(long)i * L + k] = {(float)row_i[slot] * inv, (float)row_i[L + slot] * inv};
+  dst[(long)i * L + k] = {re * inv, im * inv};
 }
 
 // Per-lane B operands of the mixed kernel, generated in FP64 (layout at
-// kConstBytes). Lane l holds column c = l & 15 and K rows 8 (l >> 4) + j
-// (j ^ 4 for tiles 8..15, the order of their operand chunks in LDS);
-// K < 16 are real inputs, K >= 16 imaginary inputs, so B1 = [Re M | -Im M]
-// gives the real and B2 = [Im M | Re M] the imaginary part of M x.
+// kConstBytes; with split a second table of residuals follows). Lane l holds
+// column c = l & 15 and K rows 8 (l >> 4) + j (j ^ 4 for tiles 8..15, the
+// order of their operand chunks in LDS); K < 16 are real inputs, K >= 16
+// imaginary inputs, so B1 = [Re M | -Im M] gives the real and
+// B2 = [Im M | Re M] the imaginary part of M x.
 template <class H>
-__global__ void mixed_consts_kernel(unsigned char *__restrict__ out) {
+__global__ void mixed_consts_kernel(unsigned char *__restrict__ out, int split) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= 2 * 16 * 64) return;
   const double kTwoPi = 6.283185307179586476925;
   const int fam = idx / 1024, tile = (idx / 64) % 16, lane = idx % 64;
   const int c = lane & 15, kg = lane >> 4;
   H *b = reinterpret_cast<H *>(out) + (size_t)idx * 16;
+  H *bl = split ? reinterpret_cast<H *>(out + kConstBytes) + (size_t)idx * 16 : nullptr;
   for (int j = 0; j < 8; ++j) {
     const int kk = kg * 8 + (j ^ (((tile >> 3) & 1) << 2)), k = kk & 15;
     // Q_t: w4096^(c (256 k + t)); P_p: w256^(k (16 c + p)) = w4096^(16 k (16 c + p))
     const int e = fam == 0 ? (c * (256 * k + tile)) & 4095 : (16 * k * (16 * c + tile)) & 4095;
     double sn, cs;
     sincos(kTwoPi * (double)e / 4096.0, &sn, &cs);
-    b[j] = (H)(kk < 16 ? cs : -sn);
-    b[8 + j] = (H)(kk < 16 ? sn : cs);
+    put_split(b + j, bl ? bl + j : nullptr, kk < 16 ? cs : -sn);
+    put_split(b + 8 + j, bl ? bl + 8 + j : nullptr, kk < 16 ? sn : cs);
   }
 }
 
-size_t mixed_consts_bytes(int L) { return L == 4096 ? (size_t)kConstBytes : 0; }
+size_t mixed_consts_bytes(int L, int split) {
+  return L == 4096 ? (size_t)kConstBytes * (split ? 2 : 1) : 0;
+}
 
-hipError_t launch_mixed_consts(void *out, int L, int precision, hipStream_t s) {
+hipError_t launch_mixed_consts(void *out, int L, int precision, int split, hipStream_t s) {
   if (L != 4096) return hipErrorInvalidValue;
   if (precision == 2)
     hipLaunchKernelGGL(mixed_consts_kernel<__bf16>, dim3(8), dim3(256), 0, s,
-                       static_cast<unsigned char *>(out));
+                       static_cast<unsigned char *>(out), split);
   else
     hipLaunchKernelGGL(mixed_consts_kernel<_Float16>, dim3(8), dim3(256), 0, s,
-                       static_cast<unsigned char *>(out));
+                       static_cast<unsigned char *>(out), split);
   return hipGetLastError();
 }
 
 hipError_t launch_bank_mixed(void *bank, const void *h, int nz, int m, int L, int precision,
-                             hipStream_t s) {
+                             int split, hipStream_t s) {
   const long n = (long)nz * L;
   const dim3 grid((unsigned)((n + 255) / 256));
   if (precision == 2)
     hipLaunchKernelGGL(bank_mixed_kernel<__bf16>, grid, dim3(256), 0, s,
-                       static_cast<__bf16 *>(bank), static_cast<const c64m *>(h), nz, m, L);
+                       static_cast<__bf16 *>(bank), static_cast<const c64m *>(h), nz, m, L, split);
   else
     hipLaunchKernelGGL(bank_mixed_kernel<_Float16>, grid, dim3(256), 0, s,
-                       static_cast<_Float16 *>(bank), static_cast<const c64m *>(h), nz, m, L);
+                       static_cast<_Float16 *>(bank), static_cast<const c64m *>(h), nz, m, L,
+                       split);
   return hipGetLastError();
 }
 
 hipError_t launch_bank_mixed_natural(c32 *dst, const void *bank, int nz, int L, int precision,
-                                     hipStream_t s) {
+                                     int split, hipStream_t s) {
   const long n = (long)nz * L;
   const dim3 grid((unsigned)((n + 255) / 256));
   if (precision == 2)
     hipLaunchKernelGGL(bank_mixed_natural_kernel<__bf16>, grid, dim3(256), 0, s, dst,
-                       static_cast<const __bf16 *>(bank), nz, L);
+                       static_cast<const __bf16 *>(bank), nz, L, split);
   else
     hipLaunchKernelGGL(bank_mixed_natural_kernel<_Float16>, grid, dim3(256), 0, s, dst,
-                       static_cast<const _Float16 *>(bank), nz, L);
+                       static_cast<const _Float16 *>(bank), nz, L, split);
   return hipGetLastError();
 }
 

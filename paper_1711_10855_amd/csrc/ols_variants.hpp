@@ -56,6 +56,7 @@ struct OlsVariant {
   const char *name;
   int L, T, G, nbuf;
   int precision;     // FDAS_FP32 (0), FDAS_MIXED_FP16 (1), FDAS_MIXED_BF16 (2)
+  int split;         // 1: hi + lo split products (FDAS_FLAG_SPLIT)
   LayoutDesc lay;
   int lds_bytes;
   hipError_t (*launch)(const OlsArgs &, hipStream_t);
@@ -67,11 +68,11 @@ struct OlsVariant {
 const OlsVariant *fp32_variants(int *count);
 const OlsVariant *mixed_variants(int *count);
 hipError_t launch_bank_mixed(void *bank, const void *h, int nz, int m, int L, int precision,
-                             hipStream_t s);
-size_t mixed_consts_bytes(int L);
-hipError_t launch_mixed_consts(void *out, int L, int precision, hipStream_t s);
+                             int split, hipStream_t s);
+size_t mixed_consts_bytes(int L, int split);
+hipError_t launch_mixed_consts(void *out, int L, int precision, int split, hipStream_t s);
 hipError_t launch_bank_mixed_natural(c32 *dst, const void *bank, int nz, int L, int precision,
-                                     hipStream_t s);
+                                     int split, hipStream_t s);
 
 hipError_t launch_templates(void *out, int nz, int m, double zmax, double dz, hipStream_t s);
 hipError_t launch_twiddles(c32 *tw, int L, hipStream_t s);

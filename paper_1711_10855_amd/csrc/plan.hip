@@ -53,12 +53,17 @@ bool mixed_supported(int seg_len) {
   return false;
 }
 
-static const OlsVariant *find_variant(int L, int precision, const char *want) {
+// FDAS_FLAG_SPLIT selects the hi + lo split-product kernels (mixed precisions).
+static int plan_split(const fdas_params &p) {
+  return (p.precision != FDAS_FP32 && (p.flags & FDAS_FLAG_SPLIT)) ? 1 : 0;
+}
+
+static const OlsVariant *find_variant(int L, int precision, int split, const char *want) {
   int n = 0;
   const OlsVariant *v = precision == FDAS_FP32 ? fp32_variants(&n) : mixed_variants(&n);
   const OlsVariant *first = nullptr;
   for (int i = 0; i < n; ++i) {
-    if (v[i].L != L || v[i].precision != precision) continue;
+    if (v[i].L != L || v[i].precision != precision || v[i].split != split) continue;
     if (want && *want && std::strcmp(v[i].name, want) == 0) return &v[i];
     if (!first) first = &v[i];
   }
@@ -176,7 +181,7 @@ static int autotune(const fdas_params &p, int nz, int device, hipStream_t s, Tun
     const OlsVariant *vs = pass == 0 ? fp32_variants(&n) : mixed_variants(&n);
     for (int i = 0; i < n && status == FDAS_OK; ++i) {
       const OlsVariant *v = &vs[i];
-      if (v->precision != p.precision) continue;
+      if (v->precision != p.precision || v->split != plan_split(p)) continue;
       if (p.seg_len ? v->L != p.seg_len : (v->L - p.m) * 2 < v->L) continue;
       int last_zpb = -1;
       for (int ng : {1, 2, 3, 4, 6, 8, 12}) {
@@ -250,7 +255,8 @@ static int build_plan_with(fdas_plan_t *out, const fdas_params &p, int nz, int d
                            hipStream_t s, const OlsVariant *force_var, int force_zpb) {
   const auto t0 = std::chrono::steady_clock::now();
   const char *want = std::getenv("FDAS_VARIANT");
-  const OlsVariant *var = force_var ? force_var : find_variant(p.seg_len, p.precision, want);
+  const OlsVariant *var =
+      force_var ? force_var : find_variant(p.seg_len, p.precision, plan_split(p), want);
   if (!var) {
     if (want && *want)
       return set_error(FDAS_ERR_UNSUPPORTED, "variant '%s' not compiled for seg_len %d", want, p.seg_len);
@@ -275,12 +281,13 @@ static int build_plan_with(fdas_plan_t *out, const fdas_params &p, int nz, int d
 
   void *h = nullptr;
   const size_t hbytes = (size_t)nz * (p.m + 1) * 16;
-  pl->bank_bytes = (size_t)nz * p.seg_len * (p.precision == FDAS_FP32 ? 8 : 6);
+  const int split = plan_split(p);
+  pl->bank_bytes = (size_t)nz * p.seg_len * (p.precision == FDAS_FP32 ? 8 : (split ? 12 : 6));
   hipError_t e = hipMalloc(&h, hbytes);
   if (e == hipSuccess) e = hipMalloc(&pl->bank, pl->bank_bytes);
   if (e == hipSuccess) e = hipMalloc(&pl->tw, (size_t)p.seg_len * 8);
   if (e == hipSuccess && p.precision != FDAS_FP32)
-    e = hipMalloc(&pl->consts, mixed_consts_bytes(p.seg_len));
+    e = hipMalloc(&pl->consts, mixed_consts_bytes(p.seg_len, split));
   if (e != hipSuccess) {
     if (h) (void)hipFree(h);
     destroy_plan(pl);
@@ -297,10 +304,11 @@ static int build_plan_with(fdas_plan_t *out, const fdas_params &p, int nz, int d
     if (p.precision == FDAS_FP32)
       e = launch_bank(static_cast<c32 *>(pl->bank), h, nz, p.m, var->lay, s);
     else
-      e = launch_bank_mixed(pl->bank, h, nz, p.m, p.seg_len, p.precision, s);
+      e = launch_bank_mixed(pl->bank, h, nz, p.m, p.seg_len, p.precision, split, s);
   }
   if (e == hipSuccess) e = launch_twiddles(static_cast<c32 *>(pl->tw), p.seg_len, s);
-  if (e == hipSuccess && pl->consts) e = launch_mixed_consts(pl->consts, p.seg_len, p.precision, s);
+  if (e == hipSuccess && pl->consts)
+    e = launch_mixed_consts(pl->consts, p.seg_len, p.precision, split, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   (void)hipFree(h);
   if (e != hipSuccess) {
@@ -359,7 +367,7 @@ int plan_bank_natural(fdas_plan_t pl, void *dst, hipStream_t s) {
                                            static_cast<const c32 *>(pl->bank), pl->nz,
                                            pl->var->lay, s)
                      : launch_bank_mixed_natural(static_cast<c32 *>(dst), pl->bank, pl->nz, pl->L,
-                                                 pl->p.precision, s);
+                                                 pl->p.precision, plan_split(pl->p), s);
   if (e != hipSuccess) return hip_error(e, "bank copy kernel");
   return FDAS_OK;
 }

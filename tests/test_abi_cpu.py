@@ -73,6 +73,7 @@ def test_resolve_defaults():
     (dict(m=64, seg_len=32768), fdas.ERR_UNSUPPORTED),
     (dict(precision=7), fdas.ERR_INVALID),
     (dict(flags=0x80), fdas.ERR_INVALID),
+    (dict(flags=fdas.FLAG_SPLIT), fdas.ERR_INVALID),  # split is for the mixed precisions
 ])
 def test_resolve_rejects(kw, status):
     with pytest.raises(fdas.FdasError) as e:
@@ -114,3 +115,8 @@ def test_kernel_variant_listing():
         sub = fdas.kernel_variants(L, "fp32")
         assert sub and all(f"_L{L}_" in n for n in sub)
     assert fdas.load().fdas_kernel_variants(-1, 0, None, 0) == fdas.ERR_INVALID
+    for prec in ("fp16", "bf16"):
+        sub = fdas.kernel_variants(4096, prec)
+        assert any("_split" in n for n in sub) and any("_split" not in n for n in sub)
+    r = fdas.resolve(100, 2, 256, 0, "bf16", fdas.FLAG_SPLIT)
+    assert (r.seg_len, r.flags) == (4096, fdas.FLAG_SPLIT)

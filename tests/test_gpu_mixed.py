@@ -1,6 +1,7 @@
-"""Mixed-precision path (16-bit storage, MFMA DFT stages, FP32 accumulation)
-against the FP64 oracle through the C ABI. Bar: max |P - P_ref| <= 1e-3 *
-max(P_ref); the measured error is printed for every case."""
+"""Mixed-precision path (16-bit storage, MFMA DFT stages, FP32 accumulation;
+optionally hi + lo split products) against the FP64 oracle through the C ABI.
+Bar: max |P - P_ref| <= 1e-3 * max(P_ref); the measured error is printed for
+every case."""
 
 import numpy as np
 import pytest
@@ -117,12 +118,77 @@ def _mixed_variants():
 @pytest.mark.parametrize("name", _mixed_variants())
 def test_every_mixed_variant(gpu, name, monkeypatch):
     prec = "bf16" if name.startswith("bf16") else "fp16"
+    split = "_split" in name
     monkeypatch.setenv("FDAS_VARIANT", name)
     a = synth.small_random_spectrum(2 * 3840 + 999, seed=31)
     ref = oracle.plane_direct(a, 8.0, 2.0, 256)
-    with gpu.Plan(8.0, 2.0, 256, 4096, prec) as p:
+    with gpu.Plan(8.0, 2.0, 256, 4096, prec, gpu.FLAG_SPLIT if split else 0) as p:
         assert p.info.kernel == name
         out = p.convolve(to_dev(a)).cpu().numpy()
     err = rel_err(out, ref)
     print(f"{name}: {err:.3e}")
-    assert err <= (TOL_MIXED if prec == "fp16" else 2e-2)
+    assert err <= (TOL_MIXED if (prec == "fp16" or split) else 2e-2)
+
+
+# ---- hi + lo split products (FDAS_FLAG_SPLIT) -------------------------------
+
+@pytest.mark.parametrize("prec,tol", [("fp16", 1e-6), ("bf16", 5e-5)])
+def test_split_bank_matches_oracle(gpu, prec, tol):
+    with gpu.Plan(100.0, 2.0, 256, 4096, prec, gpu.FLAG_SPLIT) as p:
+        assert "_split" in p.info.kernel
+        dev = p.bank().cpu().numpy().astype(np.complex128)
+    _, h = oracle.templates64(100.0, 2.0, 256)
+    ref = oracle.bank_natural(h, 256, 4096)
+    err = float(np.max(np.abs(dev - ref)) / np.max(np.abs(ref)))
+    print(f"{prec} split bank max rel err {err:.2e}")
+    assert err <= tol
+
+
+@pytest.mark.parametrize("prec,nbins,zmax,m", [
+    ("fp16", 3 * 3840 + 517, 10.0, 256),
+    ("bf16", 3 * 3840 + 517, 10.0, 256),
+    ("bf16", 20000, 30.0, 512),
+    ("bf16", 1000, 6.0, 256),
+])
+def test_split_full_plane(gpu, prec, nbins, zmax, m):
+    a = synth.small_random_spectrum(nbins, seed=nbins + 1)
+    ref = oracle.plane_direct(a, zmax, 2.0, m)
+    print(f"{prec} split nbins={nbins} zmax={zmax} m={m}", flush=True)
+    out = gpu.convolve(to_dev(a), zmax, 2.0, m, 4096, prec, gpu.FLAG_SPLIT).cpu().numpy()
+    err = rel_err(out, ref)
+    print(f"{prec} split nbins={nbins}: max|dP|/maxP = {err:.3e}")
+    assert err <= TOL_MIXED
+
+
+def test_split_workload_sampled_points(gpu):
+    """Paper-scale inputs through the BF16 split path."""
+    a, chirps = synth.single_series("fp32-paper")
+    p = gpu.convolve(to_dev(a), 100.0, 2.0, 256, 4096, "bf16", gpu.FLAG_SPLIT).cpu().numpy()
+    nz, nbins = p.shape
+    rng = np.random.default_rng(13)
+    iz = rng.integers(0, nz, 4000)
+    r = rng.integers(0, nbins, 4000)
+    extra = np.array([0, 1, nbins - 1] + [int(round(c.r0)) for c in chirps])
+    iz = np.concatenate([iz, np.repeat(np.arange(nz), extra.size)])
+    r = np.concatenate([r, np.tile(extra, nz)])
+    ref = oracle.plane_points(a, 100.0, 2.0, 256, iz, r)
+    err = float(np.max(np.abs(p[iz, r] - ref)) / ref.max())
+    print(f"mixed-paper bf16 split sampled max|dP|/maxP = {err:.3e}")
+    assert err <= TOL_MIXED
+
+
+def test_split_batch_matches_oracle(gpu):
+    import torch
+    specs = [(9000, 16.0), (1, 4.0), (4101, 0.0), (20000, 10.0)]
+    spectra = [synth.small_random_spectrum(n, seed=400 + k) for k, (n, _) in enumerate(specs)]
+    outs = [torch.full((int(round(z)) + 1, n + 3), -5.0, dtype=torch.float32, device="cuda")
+            for n, z in specs]
+    with gpu.Plan(16.0, 2.0, 256, 4096, "bf16", gpu.FLAG_SPLIT) as p:
+        p.convolve_batch([to_dev(a) for a in spectra], [z for _, z in specs], outs)
+        res = [o.cpu().numpy() for o in outs]
+    for (n, z), a, o in zip(specs, spectra, res):
+        ref = oracle.plane_direct(a, z, 2.0, 256)
+        err = rel_err(o[:, :n], ref)
+        print(f"bf16 split batch nbins={n} zmax={z}: {err:.3e}")
+        assert err <= TOL_MIXED
+        assert np.all(o[:, n:] == -5.0)
