@@ -64,6 +64,9 @@ def main():
     ap.add_argument("--command", required=True)
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--variant", required=True, help="kernel variant name the bench ran")
+    ap.add_argument("--timed-last", type=int, default=0,
+                    help="also report the mean over the last N dispatches of the hot "
+                         "kernel (the bench's timed steps, after its warm-up)")
     ap.add_argument("--bytes-per-launch", type=float, default=None,
                     help="algorithmic bytes per launch, for the ratio")
     a = ap.parse_args()
@@ -133,6 +136,16 @@ def main():
                "source_hash": source_hash(), "profile": a.name}
     if avg_ns:
         lines.append(f"Average duration of the hot kernel under the profiler: {avg_ns/1e3:.1f} us")
+    tr = _one(os.path.join(d, "prof_kt", "*kernel_trace.csv"))
+    if a.timed_last and tr:
+        with open(tr) as f:
+            durs = [(int(r["Start_Timestamp"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+                    for r in csv.DictReader(f) if a.kernel_match in r["Kernel_Name"]]
+        durs.sort()
+        last = [x for _, x in durs[-a.timed_last:]]
+        if last:
+            lines.append(f"Mean over the last {len(last)} dispatches (the timed steps after the "
+                         f"warm-up): {sum(last) / len(last) / 1e3:.1f} us")
     out_md = os.path.join(ROOT, "profiles", a.name + ".md")
     os.makedirs(os.path.dirname(out_md), exist_ok=True)
     with open(out_md, "w") as f:
