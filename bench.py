@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--zpb", type=int, default=None, help="templates per work unit")
     ap.add_argument("--precision", default=None, help="override the workload precision")
     ap.add_argument("--seg-len", type=int, default=None)
+    ap.add_argument("--split", action="store_true",
+                    help="mixed precisions: hi + lo split products (FDAS_FLAG_SPLIT)")
     ap.add_argument("--nseries", type=int, default=None, help="batched: first N series only")
     ap.add_argument("--wave-gb", type=float, default=100.0,
                     help="batched: device memory budget for the planes of one wave")
@@ -110,12 +112,12 @@ def _time(fn, steps, warmup, stream):
     return start.elapsed_time(stop) / steps, wall
 
 
-def run_single(a_dev, zmax, dz, m, seg_len, prec, steps, warmup):
+def run_single(a_dev, zmax, dz, m, seg_len, prec, steps, warmup, flags=0):
     """Time fdas_convolve on one resident spectrum; returns a result dict."""
     import torch
 
     from paper_1711_10855_amd import fdas
-    plan = fdas.Plan(zmax, dz, m, seg_len, prec, device=0)
+    plan = fdas.Plan(zmax, dz, m, seg_len, prec, flags, device=0)
     info = plan.info
     nz, nbins = info.nz, a_dev.numel()
     out = torch.empty((nz, nbins), dtype=torch.float32, device=a_dev.device)
@@ -130,7 +132,7 @@ def run_single(a_dev, zmax, dz, m, seg_len, prec, steps, warmup):
             "achieved": bytes_launch / (ms * 1e-3) / 1e9, "info": info}
 
 
-def run_batch(name, prec, seg_len, nseries, steps, warmup, wave_bytes):
+def run_batch(name, prec, seg_len, nseries, steps, warmup, wave_bytes, flags=0):
     """Time fdas_convolve_batch over a batched workload, in waves that fit."""
     import numpy as np
     import torch
@@ -142,7 +144,7 @@ def run_batch(name, prec, seg_len, nseries, steps, warmup, wave_bytes):
     gen_s = time.perf_counter() - t0
     dev = torch.device("cuda:0")
     spec_dev = [torch.from_numpy(a).to(dev) for a in spectra]
-    plan = fdas.Plan(w.zmax, w.dz, w.m, seg_len, prec, device=0)
+    plan = fdas.Plan(w.zmax, w.dz, w.m, seg_len, prec, flags, device=0)
     info = plan.info
     rows = [int(round(2 * sp.zmax / w.dz)) + 1 for sp in specs]
     # plane rows padded to 256-byte multiples (ld >= nbins), so that every row
@@ -216,13 +218,17 @@ def main():
     torch.cuda.set_device(0)
     w = synth.WORKLOADS[args.workload]
     prec = args.precision or w.precision
+    if args.split and prec == "fp32":
+        print(json.dumps({"error": "--split applies to the mixed precisions only"}))
+        sys.exit(2)
+    flags = fdas.FLAG_SPLIT if args.split else 0
     compare = None
     if w.nseries == 1:
         seg_len = args.seg_len or (4096 if prec != "fp32" else w.seg_len)
         src = "fp32-paper" if args.workload == "mixed-paper" else args.workload
         a, _ = synth.single_series(src)
         a_dev = torch.from_numpy(a).to("cuda:0")
-        r = run_single(a_dev, w.zmax, w.dz, w.m, seg_len, prec, args.steps, args.warmup)
+        r = run_single(a_dev, w.zmax, w.dz, w.m, seg_len, prec, args.steps, args.warmup, flags)
         if not args.no_compare and prec == "fp32" and not args.variant and w.m < 4096:
             c = run_single(a_dev, w.zmax, w.dz, w.m, 4096, "fp16", args.steps, args.warmup)
             compare = {"fp16_mfma": {
@@ -235,7 +241,7 @@ def main():
     else:
         seg_len = args.seg_len or (4096 if prec != "fp32" else w.seg_len)
         r = run_batch(args.workload, prec, seg_len, args.nseries, args.steps, args.warmup,
-                      int(args.wave_gb * 1e9))
+                      int(args.wave_gb * 1e9), flags)
         cpu_in = (r["sample_spectrum"], r["zmax"], r["dz"], r["m"], r["info"].nz)
         cfg = {"workload": args.workload, "nseries": r["nseries"], "waves": r["waves"],
                "input_gen_s": round(r["gen_s"], 1)}
@@ -246,7 +252,8 @@ def main():
                 "plan_ms": round(info.plan_ms, 3), "wall_s_timed": round(r["wall"], 4)})
     traffic = traffic_from_profiles(info.kernel, args.workload)
     cfg["arithmetic"] = ("plain FP32" if prec == "fp32"
-                         else f"{prec} storage, MFMA DFT stages, FP32 accumulation")
+                         else f"{prec} storage, MFMA DFT stages, FP32 accumulation"
+                         + (", hi+lo split products" if args.split else ""))
     line = {
         "metric": "z\u2013r plane points/s, batched mixed-precision vs plain FP32; "
                   "% of HBM roofline",
@@ -259,7 +266,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if prec == "fp32" else f"{prec}+f32acc",
+        "dtype": "f32" if prec == "fp32" else f"{prec}{'x3' if args.split else ''}+f32acc",
         "data": "synthetic",
         "config": cfg,
         "roofline": {"bound": "hbm", "achieved": r["achieved"], "peak": HBM_PEAK_GBS,
