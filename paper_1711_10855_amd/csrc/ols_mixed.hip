@@ -327,7 +327,11 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
 
   // X stays in registers for the whole template loop: rows 16 k0 + c of the
   // wave's tiles k0 = TPW w + j, chunk h, both planes (with SPLIT in FP32,
-  // in the order the operand chunks use).
+  // in the order the operand chunks use). Lanes g < 2 form the real part of
+  // Y = X T, Re X Re T - Im X Im T, and keep -Im X; lanes g >= 2 form
+  // Re X Im T + Im X Re T. Both then compute xr * tu + xi * tv from the bank
+  // planes (tu, tv) = (Re, Im) or (Im, Re).
+  const bool re_lane = g < 2;
   v8 xr[SPLIT ? 1 : TPW], xi[SPLIT ? 1 : TPW];
   float xrf[SPLIT ? TPW : 1][8], xif[SPLIT ? TPW : 1][8];
 #pragma unroll
@@ -339,18 +343,18 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
       for (int i = 0; i < 8; ++i) {
         const c32 v = Xf[row * 17 + 8 * h + (i ^ sw)];
         xrf[j][i] = v.x;
-        xif[j][i] = v.y;
+        xif[j][i] = re_lane ? -v.y : v.y;
       }
     } else {
       xr[j] = load8<H>(Xp, row, h);
       xi[j] = load8<H>(Xp + kPlane, row, h);
+      if (re_lane) xi[j] = -xi[j];
     }
   }
 
-  // Bank rows for the same lanes; re lanes (g < 2) compute xr*tr + xi*(-ti),
-  // im lanes xr*ti + xi*tr: plane offsets (SPLIT: lo parts 3 planes further).
-  constexpr int BP = SPLIT ? 6 : 3;  // planes per bank row
-  const int pu = (g < 2 ? 0 : 1) * L, pv = (g < 2 ? 2 : 0) * L;
+  // Bank planes Re, Im (SPLIT: their residuals 2 planes further).
+  constexpr int BP = SPLIT ? 4 : 2;  // planes per bank row
+  const int pu = (re_lane ? 0 : 1) * L, pv = (re_lane ? 1 : 0) * L;
   v8 btr[TPW], bti[TPW], btrl[SPLIT ? TPW : 1], btil[SPLIT ? TPW : 1];
   auto load_bank = [&](int iz) {
     const auto brow = bank + (int64_t)iz * (BP * L);
@@ -360,8 +364,8 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
       btr[j] = *reinterpret_cast<gptr<const v8>>(brow + pu + row * 16 + 8 * h);
       bti[j] = *reinterpret_cast<gptr<const v8>>(brow + pv + row * 16 + 8 * h);
       if constexpr (SPLIT) {
-        btrl[j] = *reinterpret_cast<gptr<const v8>>(brow + 3 * L + pu + row * 16 + 8 * h);
-        btil[j] = *reinterpret_cast<gptr<const v8>>(brow + 3 * L + pv + row * 16 + 8 * h);
+        btrl[j] = *reinterpret_cast<gptr<const v8>>(brow + 2 * L + pu + row * 16 + 8 * h);
+        btil[j] = *reinterpret_cast<gptr<const v8>>(brow + 2 * L + pv + row * 16 + 8 * h);
       }
     }
   };
@@ -557,6 +561,10 @@ static OlsVariant make_mixed(const char *name, int precision) {
   v.nbuf = 1;
   v.precision = precision;
   v.split = SPLIT ? 1 : 0;
+  // The forward FFT costs several templates' worth of time here; units of
+  // about 50 templates measured fastest (17 to 101 swept on the paper-scale
+  // plane).
+  v.zpb_target = 52;
   v.lay.L = 4096;
   v.lay.T = 256;
   v.lay.E = 16;
@@ -577,8 +585,8 @@ static const OlsVariant kMixedVariants[] = {
     make_mixed<_Float16, true, true, 8, 4, false>("fp16_L4096_mfma_w8_pf", 1),
     make_mixed<_Float16, false, true, 8, 4, false>("fp16_L4096_mfma_w8", 1),
     make_mixed<_Float16, true, false, 16, 8, false>("fp16_L4096_mfma_w16_pf_ts", 1),
-    make_mixed<__bf16, true, true, 8, 4, false>("bf16_L4096_mfma_w8_pf", 2),
     make_mixed<__bf16, true, true, 16, 8, false>("bf16_L4096_mfma_w16_pf", 2),
+    make_mixed<__bf16, true, true, 8, 4, false>("bf16_L4096_mfma_w8_pf", 2),
     // hi + lo split products (FDAS_FLAG_SPLIT)
     make_mixed<_Float16, false, true, 16, 4, true>("fp16_L4096_mfma_split_w16", 1),
     make_mixed<_Float16, true, true, 16, 4, true>("fp16_L4096_mfma_split_w16_pf", 1),
@@ -596,8 +604,8 @@ const OlsVariant *mixed_variants(int *count) {
 // k = k0 + 16 k1 + 256 k2 and slot = k2, its two 4-value halves swapped
 // when bit 7 of the row is set (the order in which the kernel reads X);
 // value conj(FFT_L(h_i))[k] (no 1/L; the kernel removes the factor
-// 2^bank_log2 = L from the power). Planes: Re, Im, -Im (rounded to 16 bits);
-// with split, three more planes hold the residuals v - round16(v).
+// 2^bank_log2 = L from the power). Planes: Re, Im (rounded to 16 bits);
+// with split, two more planes hold the residuals v - round16(v).
 struct c64m {
   double x, y;
 };
@@ -635,11 +643,10 @@ __global__ void bank_mixed_kernel(H *__restrict__ bank, const c64m *__restrict__
     sr += v.x * cs - v.y * sn;
     si += v.x * sn + v.y * cs;
   }
-  H *row_i = bank + (long)i * (split ? 6 : 3) * L;
-  H *lo = split ? row_i + 3 * L : nullptr;
-  put_split(row_i + slot, lo ? lo + slot : nullptr, sr);                // Re T'
-  put_split(row_i + L + slot, lo ? lo + L + slot : nullptr, -si);       // Im T'
-  put_split(row_i + 2 * L + slot, lo ? lo + 2 * L + slot : nullptr, si);  // -Im T'
+  H *row_i = bank + (long)i * (split ? 4 : 2) * L;
+  H *lo = split ? row_i + 2 * L : nullptr;
+  put_split(row_i + slot, lo ? lo + slot : nullptr, sr);            // Re T'
+  put_split(row_i + L + slot, lo ? lo + L + slot : nullptr, -si);   // Im T'
 }
 
 template <class H>
@@ -650,11 +657,11 @@ __global__ void bank_mixed_natural_kernel(c32 *__restrict__ dst, const H *__rest
   const int i = (int)(idx / L);
   const int slot = (int)(idx % L);
   const int k = bank_slot_k(slot);
-  const H *row_i = bank + (long)i * (split ? 6 : 3) * L;
+  const H *row_i = bank + (long)i * (split ? 4 : 2) * L;
   float re = (float)row_i[slot], im = (float)row_i[L + slot];
   if (split) {
-    re += (float)row_i[3 * L + slot];
-    im += (float)row_i[4 * L + slot];
+    re += (float)row_i[2 * L + slot];
+    im += (float)row_i[3 * L + slot];
   }
   const float inv = 1.0f / (float)L;
   dst[(long)i * L + k] = {re * inv, im * inv};

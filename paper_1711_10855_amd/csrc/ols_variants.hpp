@@ -57,6 +57,8 @@ struct OlsVariant {
   int L, T, G, nbuf;
   int precision;     // FDAS_FP32 (0), FDAS_MIXED_FP16 (1), FDAS_MIXED_BF16 (2)
   int split;         // 1: hi + lo split products (FDAS_FLAG_SPLIT)
+  int zpb_target;    // > 0: templates per work unit fixed near this (balanced
+                     // groups); 0: chosen per launch from the grid's rounds
   LayoutDesc lay;
   int lds_bytes;
   hipError_t (*launch)(const OlsArgs &, hipStream_t);

@@ -70,9 +70,11 @@ static const OlsVariant *find_variant(int L, int precision, int split, const cha
   return (want && *want) ? nullptr : first;
 }
 
-// Templates per work unit: split nz into ceil(nz / 32) near-equal groups.
-static int default_zpb(int nz) {
-  const int groups = (nz + 31) / 32;
+// Templates per work unit: split nz into near-equal groups of at most
+// `target` (32 unless the variant fixes its own).
+static int default_zpb(int nz, int target) {
+  if (target <= 0) target = 32;
+  const int groups = (nz + target - 1) / target;
   return (nz + groups - 1) / groups;
 }
 
@@ -271,7 +273,7 @@ static int build_plan_with(fdas_plan_t *out, const fdas_params &p, int nz, int d
   pl->L = p.seg_len;
   pl->U = p.seg_len - p.m;
   pl->var = var;
-  pl->zpb = default_zpb(nz);
+  pl->zpb = default_zpb(nz, var->zpb_target);
   if (const char *z = std::getenv("FDAS_ZPB")) {
     const int v = std::atoi(z);
     if (v > 0) pl->zpb = v;
@@ -282,7 +284,7 @@ static int build_plan_with(fdas_plan_t *out, const fdas_params &p, int nz, int d
   void *h = nullptr;
   const size_t hbytes = (size_t)nz * (p.m + 1) * 16;
   const int split = plan_split(p);
-  pl->bank_bytes = (size_t)nz * p.seg_len * (p.precision == FDAS_FP32 ? 8 : (split ? 12 : 6));
+  pl->bank_bytes = (size_t)nz * p.seg_len * (p.precision == FDAS_FP32 ? 8 : (split ? 8 : 4));
   hipError_t e = hipMalloc(&h, hbytes);
   if (e == hipSuccess) e = hipMalloc(&pl->bank, pl->bank_bytes);
   if (e == hipSuccess) e = hipMalloc(&pl->tw, (size_t)p.seg_len * 8);
@@ -376,7 +378,7 @@ int plan_bank_natural(fdas_plan_t pl, void *dst, hipStream_t s) {
 // ceil(blocks / slots) rounds, each as long as one unit (zpb inverse FFTs plus
 // about one forward FFT); pick the group count that minimises that product.
 static int launch_zpb(fdas_plan_t pl, int64_t nsb) {
-  if (pl->zpb_forced) return pl->zpb;
+  if (pl->zpb_forced || pl->var->zpb_target > 0) return pl->zpb;
   if (!pl->slots) {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, pl->device) != hipSuccess)
