@@ -136,3 +136,34 @@ def test_batch_workload_sample(gpu):
         err = float(np.max(np.abs(o[iz, r] - ref)) / ref.max())
         print(f"series nbins={sp.nbins} zmax={sp.zmax}: {err:.3e}")
         assert err <= TOL_FP32
+
+
+@pytest.mark.parametrize("prec,split,tol", [("fp16", False, 1e-3), ("bf16", True, 1e-3),
+                                           ("fp32", False, TOL_FP32)])
+def test_wide_batch_workload_sample(gpu, prec, split, tol):
+    """Wide-filter batched recipe (2^21 bins per series, z in [-200, 200],
+    m 512) on three of its series in the bench's launch configuration
+    (segment length 4096 for the 16-bit forms, the FP32 default otherwise),
+    sampled points checked against the oracle."""
+    import torch
+    specs = synth.batch_specs("batch-mixed-wide", nseries=3)
+    spectra = [synth.batch_spectrum("batch-mixed-wide", sp) for sp in specs]
+    ld = [(sp.nbins + 63) // 64 * 64 for sp in specs]
+    outs = [torch.empty((201, l), dtype=torch.float32, device="cuda")[:, :sp.nbins]
+            for sp, l in zip(specs, ld)]
+    print(f"batch-mixed-wide sample of 3 series, {prec} split={split}", flush=True)
+    flags = gpu.FLAG_SPLIT if split else 0
+    with gpu.Plan(200.0, 2.0, 512, 4096 if prec != "fp32" else 0, prec, flags) as p:
+        p.convolve_batch([to_dev(a) for a in spectra], [sp.zmax for sp in specs], outs)
+        res = [o.cpu().numpy() for o in outs]
+    rng = np.random.default_rng(5)
+    for sp, a, o in zip(specs, spectra, res):
+        iz = rng.integers(0, 201, 1200)
+        r = rng.integers(0, sp.nbins, 1200)
+        extra = np.array([0, sp.nbins - 1] + [int(round(c.r0)) for c in sp.chirps])
+        iz = np.concatenate([iz, np.repeat(np.arange(201), extra.size)])
+        r = np.concatenate([r, np.tile(extra, 201)])
+        ref = oracle.plane_points(a, 200.0, 2.0, 512, iz, r)
+        err = float(np.max(np.abs(o[iz, r] - ref)) / ref.max())
+        print(f"{prec} series nbins={sp.nbins}: {err:.3e}")
+        assert err <= tol
