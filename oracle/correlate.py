@@ -58,21 +58,26 @@ def correlate_direct(a: np.ndarray, h: np.ndarray, m: int) -> np.ndarray:
     return out
 
 
-def plane_direct(a: np.ndarray, zmax: float, dz: float, m: int) -> np.ndarray:
-    """The z-r power plane P[i, r] = |B_{z_i}(r)|^2 by the direct eq. 2 sum."""
-    _, h = templates64(zmax, dz, m)
+def plane_direct(a: np.ndarray, zmax: float, dz: float, m: int,
+                 interbin: bool = False) -> np.ndarray:
+    """The z-r power plane P[i, r] = |B_{z_i}(r)|^2 by the direct eq. 2 sum.
+
+    ``interbin``: 2 nz rows, row 2i + 1 holding the power at r + 1/2 (see
+    ``templates64``)."""
+    _, h = templates64(zmax, dz, m, interbin)
     b = correlate_direct(a, h, m)
     return (b.real ** 2 + b.imag ** 2)
 
 
 def plane_points(a: np.ndarray, zmax: float, dz: float, m: int,
-                 iz: np.ndarray, r: np.ndarray, chunk: int = 4096) -> np.ndarray:
+                 iz: np.ndarray, r: np.ndarray, chunk: int = 4096,
+                 interbin: bool = False) -> np.ndarray:
     """P at selected plane points (iz[k], r[k]) by the direct eq. 2 sum.
 
     Used for spot checks at sizes where the full plane is too large.
     """
     half = _check_m(m)
-    _, h = templates64(zmax, dz, m)
+    _, h = templates64(zmax, dz, m, interbin)
     hc = np.conj(h)
     a = np.asarray(a, dtype=np.complex128)
     n = a.size
@@ -99,7 +104,7 @@ def _dft_matrix(n: int, sign: int) -> np.ndarray:
 
 
 def plane_ols_naive(a: np.ndarray, zmax: float, dz: float, m: int,
-                    seg_len: int) -> np.ndarray:
+                    seg_len: int, interbin: bool = False) -> np.ndarray:
     """The same plane by overlap-and-save with naive O(L^2) DFTs (Section 2).
 
     Segment s reads x_j = A[s U - m/2 + j], j in [0, L), U = L - m, zero
@@ -113,7 +118,7 @@ def plane_ols_naive(a: np.ndarray, zmax: float, dz: float, m: int,
     L = int(seg_len)
     if L <= m:
         raise ValueError("seg_len must exceed m")
-    _, h = templates64(zmax, dz, m)
+    _, h = templates64(zmax, dz, m, interbin)
     a = np.asarray(a, dtype=np.complex128)
     n = a.size
     U = L - m

@@ -95,21 +95,30 @@ def template_h(z: float, q) -> np.ndarray:
     return ph * response_g(z, q)
 
 
-def templates64(zmax: float, dz: float, m: int):
+def templates64(zmax: float, dz: float, m: int, interbin: bool = False):
     """The template bank in the time (bin-offset) domain, FP64.
 
     Returns ``(z, H)`` with ``z`` the nz trial drifts and ``H[i, j] =
     H_{z_i}(j - m/2)`` for j in [0, m] (m + 1 taps, offsets -m/2..m/2, the
     bounds of the eq. 2 sum).
+
+    ``interbin``: the response is also wanted half-way between bins (the
+    corrected response of Section 1 at a non-integer r). Row 2i is then
+    template z_i at integer r and row 2i + 1 the same template at r + 1/2,
+    over the same m + 1 bins [r - m/2, r + m/2]: offsets k - (r + 1/2) =
+    q - 1/2, so H[2i + 1, j] = H_{z_i}(j - m/2 - 1/2). ``z`` then lists each
+    drift twice.
     """
     if m < 2 or m % 2:
         raise ValueError("m must be even and >= 2")
     z = z_grid(zmax, dz)
     q = np.arange(-(m // 2), m // 2 + 1, dtype=np.float64)
-    h = np.empty((z.size, m + 1), dtype=np.complex128)
+    shifts = (0.0, 0.5) if interbin else (0.0,)
+    h = np.empty((z.size * len(shifts), m + 1), dtype=np.complex128)
     for i, zi in enumerate(z):
-        h[i] = template_h(zi, q)
-    return z, h
+        for p, sh in enumerate(shifts):
+            h[len(shifts) * i + p] = template_h(zi, q - sh)
+    return np.repeat(z, len(shifts)), h
 
 
 def response_g_quadrature(z: float, q, order: int = 32) -> np.ndarray:
