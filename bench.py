@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--seg-len", type=int, default=None)
     ap.add_argument("--split", action="store_true",
                     help="mixed precisions: hi + lo split products (FDAS_FLAG_SPLIT)")
+    ap.add_argument("--interbin", action="store_true",
+                    help="also the half-bin rows (FDAS_FLAG_INTERBIN): 2 nz rows per plane")
     ap.add_argument("--nseries", type=int, default=None, help="batched: first N series only")
     ap.add_argument("--wave-gb", type=float, default=100.0,
                     help="batched: device memory budget for the planes of one wave")
@@ -146,7 +148,8 @@ def run_batch(name, prec, seg_len, nseries, steps, warmup, wave_bytes, flags=0):
     spec_dev = [torch.from_numpy(a).to(dev) for a in spectra]
     plan = fdas.Plan(w.zmax, w.dz, w.m, seg_len, prec, flags, device=0)
     info = plan.info
-    rows = [int(round(2 * sp.zmax / w.dz)) + 1 for sp in specs]
+    per = 2 if flags & fdas.FLAG_INTERBIN else 1
+    rows = [per * (int(round(2 * sp.zmax / w.dz)) + 1) for sp in specs]
     # plane rows padded to 256-byte multiples (ld >= nbins), so that every row
     # starts on a cache-line boundary
     lds = [(sp.nbins + 63) // 64 * 64 for sp in specs]
@@ -221,7 +224,7 @@ def main():
     if args.split and prec == "fp32":
         print(json.dumps({"error": "--split applies to the mixed precisions only"}))
         sys.exit(2)
-    flags = fdas.FLAG_SPLIT if args.split else 0
+    flags = (fdas.FLAG_SPLIT if args.split else 0) | (fdas.FLAG_INTERBIN if args.interbin else 0)
     compare = None
     if w.nseries == 1:
         seg_len = args.seg_len or (4096 if prec != "fp32" else w.seg_len)
@@ -230,7 +233,8 @@ def main():
         a_dev = torch.from_numpy(a).to("cuda:0")
         r = run_single(a_dev, w.zmax, w.dz, w.m, seg_len, prec, args.steps, args.warmup, flags)
         if not args.no_compare and prec == "fp32" and not args.variant and w.m < 4096:
-            c = run_single(a_dev, w.zmax, w.dz, w.m, 4096, "fp16", args.steps, args.warmup)
+            c = run_single(a_dev, w.zmax, w.dz, w.m, 4096, "fp16", args.steps, args.warmup,
+                           flags & fdas.FLAG_INTERBIN)
             compare = {"fp16_mfma": {
                 "value": c["value"], "ms_per_step": c["ms"], "seg_len": 4096,
                 "kernel": c["info"].kernel, "frac": c["achieved"] / HBM_PEAK_GBS,
@@ -254,6 +258,8 @@ def main():
     cfg["arithmetic"] = ("plain FP32" if prec == "fp32"
                          else f"{prec} storage, MFMA DFT stages, FP32 accumulation"
                          + (", hi+lo split products" if args.split else ""))
+    if args.interbin:
+        cfg["rows"] = "2 nz: integer and half-bin (r + 1/2) responses"
     line = {
         "metric": "z\u2013r plane points/s, batched mixed-precision vs plain FP32; "
                   "% of HBM roofline",

@@ -61,6 +61,12 @@ extern "C" {
                                  block) on a synthetic spectrum of 2^20 bins and
                                  keep the fastest per plane point; cached in the
                                  file named by FDAS_TUNE_CACHE when set */
+#define FDAS_FLAG_INTERBIN 4u /* also the response half-way between bins (the
+                                 corrected response of Section 1 at r + 1/2):
+                                 the plane has 2 nz rows, row 2i holding z_i at
+                                 integer r and row 2i + 1 the same z_i at
+                                 r + 1/2, from the same m + 1 bins
+                                 [r - m/2, r + m/2] (offsets q - 1/2) */
 
 /* Filter-bank parameters.
  *   zmax, dz  : z grid z_i = -zmax + i*dz; zmax >= 0, dz > 0, 2*zmax/dz an
@@ -88,7 +94,8 @@ typedef struct {
  *   nbins    : >= 1.
  *   zmax     : this series' zmax; <= the plan's zmax and on its grid
  *              ((plan.zmax - zmax)/dz an integer). Its plane has
- *              nz_s = 2*zmax/dz + 1 rows, row j <-> z = -zmax + j*dz.
+ *              nz_s = 2*zmax/dz + 1 rows, row j <-> z = -zmax + j*dz
+ *              (2 nz_s rows with FDAS_FLAG_INTERBIN, as for the full plane).
  *   power    : device float [nz_s][ld], ld >= nbins.                        */
 typedef struct {
   const void *spectrum;
@@ -116,8 +123,9 @@ typedef struct {
 
 typedef struct fdas_plan_s *fdas_plan_t;
 
-/* Number of plane rows nz = 2*zmax/dz + 1 for valid params, else a negative
- * status. Host only; never touches the device.                              */
+/* Number of plane rows for valid params: nz = 2*zmax/dz + 1, or 2 nz with
+ * FDAS_FLAG_INTERBIN; else a negative status. Host only; never touches the
+ * device.                                                                    */
 int fdas_plane_rows(const fdas_params *p);
 
 /* Fill defaults (m, seg_len) and validate; *out receives the resolved
@@ -160,11 +168,13 @@ int fdas_plan_bank(fdas_plan_t plan, void *dst, size_t bytes, void *stream);
 int fdas_convolve(fdas_plan_t plan, const void *spectrum, int64_t nbins,
                   float *power, int64_t ld, void *stream);
 
-/* Batched hot path: one persistent launch over every (series, segment,
- * template group) work item, largest series first, items taken from a device
- * counter. Each series uses the central nz_s rows of the plan's bank. The
- * launch is captured once into a HIP graph per distinct batch shape and
- * replayed. `series` is host memory with nseries >= 1 entries.              */
+/* Batched hot path: one launch over every (series, template group, segment)
+ * work item, largest series first (a flat grid of items; the FP32 kernels can
+ * instead run persistent blocks taking items from a device counter when the
+ * environment sets FDAS_BATCH_PERSISTENT=1). Each series uses the central
+ * rows of the plan's bank. The launch is captured once into a HIP graph per
+ * distinct batch shape and replayed. `series` is host memory with
+ * nseries >= 1 entries.                                                      */
 int fdas_convolve_batch(fdas_plan_t plan, const fdas_series *series,
                         int nseries, void *stream);
 

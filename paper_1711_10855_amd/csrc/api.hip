@@ -53,10 +53,12 @@ static int validate_grid(double zmax, double dz) {
 int resolve_params(const fdas_params *in, fdas_params *out, int *nz_out) {
   if (!in || !out) return set_error(FDAS_ERR_INVALID, "null params pointer");
   fdas_params p = *in;
-  const int nz = validate_grid(p.zmax, p.dz);
-  if (nz < 0) return nz;
-  if (p.flags & ~(FDAS_FLAG_SPLIT | FDAS_FLAG_AUTOTUNE))
+  const int ntz = validate_grid(p.zmax, p.dz);
+  if (ntz < 0) return ntz;
+  if (p.flags & ~(FDAS_FLAG_SPLIT | FDAS_FLAG_AUTOTUNE | FDAS_FLAG_INTERBIN))
     return set_error(FDAS_ERR_INVALID, "unknown flag bits 0x%x", p.flags);
+  // bank and plane rows: one per trial drift, two with half-bin rows
+  const int nz = (p.flags & FDAS_FLAG_INTERBIN) ? 2 * ntz : ntz;
   if (p.precision != FDAS_FP32 && p.precision != FDAS_MIXED_FP16 &&
       p.precision != FDAS_MIXED_BF16)
     return set_error(FDAS_ERR_INVALID, "unknown precision %d", p.precision);
@@ -140,7 +142,9 @@ int fdas_kernel_variants(int seg_len, int precision, char *buf, size_t len) {
 
 int fdas_plane_rows(const fdas_params *p) {
   if (!p) return set_error(FDAS_ERR_INVALID, "null params pointer");
-  return validate_grid(p->zmax, p->dz);
+  const int nz = validate_grid(p->zmax, p->dz);
+  if (nz < 0) return nz;
+  return (p->flags & FDAS_FLAG_INTERBIN) ? 2 * nz : nz;
 }
 
 int fdas_resolve_params(const fdas_params *in, fdas_params *out) {
@@ -164,7 +168,8 @@ int fdas_make_templates(const fdas_params *p, void *templates, size_t *bytes, vo
     return set_error(FDAS_ERR_INVALID, "templates buffer holds %zu bytes, need %zu", have, need);
   }
   *bytes = need;
-  hipError_t e = launch_templates(templates, nz, r.m, r.zmax, r.dz, (hipStream_t)stream);
+  hipError_t e = launch_templates(templates, nz, r.m, r.zmax, r.dz,
+                                  (r.flags & FDAS_FLAG_INTERBIN) ? 1 : 0, (hipStream_t)stream);
   if (e != hipSuccess) return hip_error(e, "template kernel launch");
   return FDAS_OK;
 }

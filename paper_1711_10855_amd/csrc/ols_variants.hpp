@@ -76,7 +76,8 @@ hipError_t launch_mixed_consts(void *out, int L, int precision, int split, hipSt
 hipError_t launch_bank_mixed_natural(c32 *dst, const void *bank, int nz, int L, int precision,
                                      int split, hipStream_t s);
 
-hipError_t launch_templates(void *out, int nz, int m, double zmax, double dz, hipStream_t s);
+hipError_t launch_templates(void *out, int rows, int m, double zmax, double dz, int interbin,
+                            hipStream_t s);
 hipError_t launch_twiddles(c32 *tw, int L, hipStream_t s);
 hipError_t launch_bank(c32 *bank, const void *h, int nz, int m, const LayoutDesc &lay,
                        hipStream_t s);

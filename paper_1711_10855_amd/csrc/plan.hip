@@ -301,7 +301,7 @@ static int build_plan_with(fdas_plan_t *out, const fdas_params &p, int nz, int d
     destroy_plan(pl);
     return set_error(FDAS_ERR_NOMEM, "plan allocation: %s", hipGetErrorString(e));
   }
-  e = launch_templates(h, nz, p.m, p.zmax, p.dz, s);
+  e = launch_templates(h, nz, p.m, p.zmax, p.dz, (p.flags & FDAS_FLAG_INTERBIN) ? 1 : 0, s);
   if (e == hipSuccess) {
     if (p.precision == FDAS_FP32)
       e = launch_bank(static_cast<c32 *>(pl->bank), h, nz, p.m, var->lay, s);
@@ -452,13 +452,14 @@ int plan_convolve_batch(fdas_plan_t pl, const fdas_series *series, int nseries, 
     const int64_t nseg = (x.nbins + pl->U - 1) / pl->U;
     if (nseg > INT_MAX / 2) return set_error(FDAS_ERR_UNSUPPORTED, "series %d too long", i);
     SeriesDesc &d = desc[i];
+    const int per = (pl->p.flags & FDAS_FLAG_INTERBIN) ? 2 : 1;  // bank rows per drift
     d.spec = x.spectrum;
     d.power = x.power;
     d.nbins = x.nbins;
     d.ld = x.ld;
     d.nseg = (int)nseg;
-    d.nz = (int)std::nearbyint(span) + 1;
-    d.row_off = (int)std::nearbyint(off);
+    d.nz = per * ((int)std::nearbyint(span) + 1);
+    d.row_off = per * (int)std::nearbyint(off);
     // near-equal template groups of at most the plan's templates per unit
     const int ng = (d.nz + pl->zpb - 1) / pl->zpb;
     d.zpb = (d.nz + ng - 1) / ng;

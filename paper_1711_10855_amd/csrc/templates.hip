@@ -133,14 +133,19 @@ __device__ c64 template_h(double z, double q) {
   return zmul(expipi(-fmod(q, 2.0)), g);
 }
 
-// H[i][j] = H_{z_i}(j - m/2), z_i = -zmax + i dz.
-__global__ void templates_kernel(c64 *__restrict__ out, int nz, int m, double zmax, double dz) {
+// H[i][j] = H_{z_i}(j - m/2), z_i = -zmax + i dz. With interbin the rows
+// come in pairs: H[2i][j] = H_{z_i}(j - m/2) and H[2i+1][j] = H_{z_i}(j - m/2
+// - 1/2), the response at r + 1/2 from the same bins.
+__global__ void templates_kernel(c64 *__restrict__ out, int rows, int m, double zmax, double dz,
+                                 int interbin) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   const int taps = m + 1;
-  if (idx >= nz * taps) return;
-  const int i = idx / taps, j = idx % taps;
+  if (idx >= rows * taps) return;
+  const int row = idx / taps, j = idx % taps;
+  const int i = interbin ? row >> 1 : row;
+  const double shift = (interbin && (row & 1)) ? 0.5 : 0.0;
   const double z = -zmax + i * dz;
-  out[idx] = template_h(z, (double)(j - m / 2));
+  out[idx] = template_h(z, (double)(j - m / 2) - shift);
 }
 
 // W_L^j = exp(-i 2 pi j / L), rounded to FP32.
@@ -192,10 +197,11 @@ __global__ void bank_natural_kernel(c32 *__restrict__ dst, const c32 *__restrict
   dst[(long)i * L + k] = bank[idx];
 }
 
-hipError_t launch_templates(void *out, int nz, int m, double zmax, double dz, hipStream_t s) {
-  const int n = nz * (m + 1);
+hipError_t launch_templates(void *out, int rows, int m, double zmax, double dz, int interbin,
+                            hipStream_t s) {
+  const int n = rows * (m + 1);
   hipLaunchKernelGGL(templates_kernel, dim3((n + 255) / 256), dim3(256), 0, s,
-                     static_cast<c64 *>(out), nz, m, zmax, dz);
+                     static_cast<c64 *>(out), rows, m, zmax, dz, interbin);
   return hipGetLastError();
 }
 

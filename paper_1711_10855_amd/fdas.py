@@ -29,6 +29,7 @@ PRECISIONS = {"fp32": FP32, "fp16": MIXED_FP16, "bf16": MIXED_BF16}
 
 FLAG_SPLIT = 1
 FLAG_AUTOTUNE = 2
+FLAG_INTERBIN = 4
 
 EXPORTS = (
     "fdas_plane_rows", "fdas_resolve_params", "fdas_make_templates", "fdas_plan",
@@ -119,8 +120,8 @@ def params(zmax, dz, m=0, seg_len=0, precision="fp32", flags=0) -> Params:
     return Params(float(zmax), float(dz), int(m or 0), int(seg_len or 0), prec, int(flags))
 
 
-def plane_rows(zmax, dz) -> int:
-    n = load().fdas_plane_rows(C.byref(params(zmax, dz)))
+def plane_rows(zmax, dz, flags=0) -> int:
+    n = load().fdas_plane_rows(C.byref(params(zmax, dz, 0, 0, "fp32", flags)))
     if n < 0:
         _check(n, "fdas_plane_rows")
     return n
@@ -149,15 +150,16 @@ def _stream(device=None):
     return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
-def make_templates(zmax, dz, m=0):
-    """FP64 templates H_{z_i}(q), complex128 tensor [nz, m+1] on the current device."""
+def make_templates(zmax, dz, m=0, flags=0):
+    """FP64 templates H_{z_i}(q), complex128 tensor [rows, m+1] on the current
+    device (rows = nz, or 2 nz with FLAG_INTERBIN)."""
     import torch
-    p = params(zmax, dz, m)
+    p = params(zmax, dz, m, 0, "fp32", flags)
     nbytes = C.c_size_t(0)
     _check(load().fdas_make_templates(C.byref(p), None, C.byref(nbytes), None),
            "fdas_make_templates(size)")
-    r = resolve(zmax, dz, m)
-    nz = plane_rows(zmax, dz)
+    r = resolve(zmax, dz, m, 0, "fp32", flags)
+    nz = plane_rows(zmax, dz, flags)
     out = torch.empty((nz, r.m + 1), dtype=torch.complex128, device="cuda")
     _check(load().fdas_make_templates(C.byref(p), C.c_void_p(out.data_ptr()), C.byref(nbytes),
                                       _stream()), "fdas_make_templates")

@@ -82,6 +82,17 @@ def test_resolve_rejects(kw, status):
     assert fdas.last_error() != ""
 
 
+def test_interbin_doubles_the_rows(lib):
+    assert fdas.plane_rows(16, 2) == 17
+    assert fdas.plane_rows(16, 2, fdas.FLAG_INTERBIN) == 34
+    r = fdas.resolve(16, 2, 64, 256, "fp32", fdas.FLAG_INTERBIN)
+    assert r.flags == fdas.FLAG_INTERBIN
+    p = fdas.params(16, 2, 64, 0, "fp32", fdas.FLAG_INTERBIN)
+    n = C.c_size_t(0)
+    assert lib.fdas_make_templates(C.byref(p), None, C.byref(n), None) == 0
+    assert n.value == 34 * 65 * 16
+
+
 def test_template_size_query_needs_no_device(lib):
     p = fdas.params(16, 2, 64)
     n = C.c_size_t(0)
