@@ -52,6 +52,9 @@ def parse():
                     help="mixed precisions: hi + lo split products (FDAS_FLAG_SPLIT)")
     ap.add_argument("--interbin", action="store_true",
                     help="also the half-bin rows (FDAS_FLAG_INTERBIN): 2 nz rows per plane")
+    ap.add_argument("--candidates", type=float, default=None, metavar="THR",
+                    help="single series: detection epilogue (points with power >= THR "
+                         "listed) instead of writing the plane")
     ap.add_argument("--nseries", type=int, default=None, help="batched: first N series only")
     ap.add_argument("--wave-gb", type=float, default=100.0,
                     help="batched: device memory budget for the planes of one wave")
@@ -114,24 +117,31 @@ def _time(fn, steps, warmup, stream):
     return start.elapsed_time(stop) / steps, wall
 
 
-def run_single(a_dev, zmax, dz, m, seg_len, prec, steps, warmup, flags=0):
-    """Time fdas_convolve on one resident spectrum; returns a result dict."""
+def run_single(a_dev, zmax, dz, m, seg_len, prec, steps, warmup, flags=0, cand_thr=None):
+    """Time fdas_convolve (or the candidate epilogue) on one resident
+    spectrum; returns a result dict."""
     import torch
 
     from paper_1711_10855_amd import fdas
     plan = fdas.Plan(zmax, dz, m, seg_len, prec, flags, device=0)
     info = plan.info
     nz, nbins = info.nz, a_dev.numel()
-    out = torch.empty((nz, nbins), dtype=torch.float32, device=a_dev.device)
     stream = torch.cuda.current_stream(a_dev.device)
-    ms, wall = _time(lambda: plan.convolve(a_dev, out=out), steps, warmup, stream)
+    ncand = None
+    if cand_thr is None:
+        out = torch.empty((nz, nbins), dtype=torch.float32, device=a_dev.device)
+        ms, wall = _time(lambda: plan.convolve(a_dev, out=out), steps, warmup, stream)
+        del out
+    else:
+        buf = plan.candidates(a_dev, cand_thr, capacity=1 << 20)
+        ms, wall = _time(lambda: plan.candidates(a_dev, cand_thr, buf=buf), steps, warmup, stream)
+        ncand = int(buf[1].cpu()[0])
     plan.close()
-    del out
     points = nz * nbins
-    bytes_launch = 4.0 * points + 8.0 * nbins
+    bytes_launch = (4.0 * points if cand_thr is None else 16.0 * ncand) + 8.0 * nbins
     return {"points": points, "nz": nz, "nbins": nbins, "ms": ms, "wall": wall,
             "value": points / (ms * 1e-3), "bytes_launch": bytes_launch,
-            "achieved": bytes_launch / (ms * 1e-3) / 1e9, "info": info}
+            "achieved": bytes_launch / (ms * 1e-3) / 1e9, "info": info, "ncand": ncand}
 
 
 def run_batch(name, prec, seg_len, nseries, steps, warmup, wave_bytes, flags=0):
@@ -231,10 +241,11 @@ def main():
         src = "fp32-paper" if args.workload == "mixed-paper" else args.workload
         a, _ = synth.single_series(src)
         a_dev = torch.from_numpy(a).to("cuda:0")
-        r = run_single(a_dev, w.zmax, w.dz, w.m, seg_len, prec, args.steps, args.warmup, flags)
+        r = run_single(a_dev, w.zmax, w.dz, w.m, seg_len, prec, args.steps, args.warmup, flags,
+                       args.candidates)
         if not args.no_compare and prec == "fp32" and not args.variant and w.m < 4096:
             c = run_single(a_dev, w.zmax, w.dz, w.m, 4096, "fp16", args.steps, args.warmup,
-                           flags & fdas.FLAG_INTERBIN)
+                           flags & fdas.FLAG_INTERBIN, args.candidates)
             compare = {"fp16_mfma": {
                 "value": c["value"], "ms_per_step": c["ms"], "seg_len": 4096,
                 "kernel": c["info"].kernel, "frac": c["achieved"] / HBM_PEAK_GBS,
@@ -260,6 +271,9 @@ def main():
                          + (", hi+lo split products" if args.split else ""))
     if args.interbin:
         cfg["rows"] = "2 nz: integer and half-bin (r + 1/2) responses"
+    if args.candidates is not None:
+        cfg["epilogue"] = (f"threshold: points with power >= {args.candidates} listed, "
+                           f"no plane written ({r.get('ncand')} found)")
     line = {
         "metric": "z\u2013r plane points/s, batched mixed-precision vs plain FP32; "
                   "% of HBM roofline",

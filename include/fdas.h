@@ -168,6 +168,26 @@ int fdas_plan_bank(fdas_plan_t plan, void *dst, size_t bytes, void *stream);
 int fdas_convolve(fdas_plan_t plan, const void *spectrum, int64_t nbins,
                   float *power, int64_t ld, void *stream);
 
+/* One detection candidate: plane row (as in the power plane), bin, power. */
+typedef struct {
+  int32_t row;
+  float power;
+  int64_t r;
+} fdas_candidate;
+
+/* The hot path with a detection epilogue instead of the plane (the step that
+ * follows the plane in the FDAS pipeline, Section 3; only the threshold part
+ * of it): every plane point with power >= threshold is appended to `cands`.
+ *   cands    : device fdas_candidate [capacity] (16-byte aligned); the first
+ *              min(*count, capacity) entries are written, in no fixed order.
+ *   count    : device uint64; set to the number of plane points at or above
+ *              the threshold (also those that did not fit).
+ * The count is cleared on `stream` by a kernel before the correlation, so the
+ * call can be captured into a graph. Asynchronous; no allocation, no copy.   */
+int fdas_convolve_candidates(fdas_plan_t plan, const void *spectrum, int64_t nbins,
+                             float threshold, fdas_candidate *cands, int64_t capacity,
+                             unsigned long long *count, void *stream);
+
 /* Batched hot path: one launch over every (series, template group, segment)
  * work item, largest series first (a flat grid of items; the FP32 kernels can
  * instead run persistent blocks taking items from a device counter when the

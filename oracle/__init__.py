@@ -32,4 +32,5 @@ from .correlate import (  # noqa: F401
     correlate_bruteforce,
     correlate_at,
     bank_natural,
+    candidates_direct,
 )

@@ -190,3 +190,13 @@ def bank_natural(h: np.ndarray, m: int, seg_len: int) -> np.ndarray:
     for j in range(m + 1):
         hw[:, (j - half) % L] += h[:, j]
     return np.conj(np.fft.fft(hw, axis=1)) / L
+
+
+def candidates_direct(a: np.ndarray, zmax: float, dz: float, m: int, threshold: float,
+                      interbin: bool = False):
+    """Detection step after the plane (Section 3 names it; only its threshold
+    part): every plane point with P >= threshold, as (row, r, P) arrays in
+    row-major order, from the direct eq. 2 plane."""
+    p = plane_direct(a, zmax, dz, m, interbin)
+    row, r = np.nonzero(p >= threshold)
+    return row, r, p[row, r]

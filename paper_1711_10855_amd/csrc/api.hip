@@ -219,6 +219,24 @@ int fdas_convolve(fdas_plan_t plan, const void *spectrum, int64_t nbins, float *
   return plan_convolve(plan, spectrum, nbins, power, ld, (hipStream_t)stream);
 }
 
+int fdas_convolve_candidates(fdas_plan_t plan, const void *spectrum, int64_t nbins, float threshold,
+                             fdas_candidate *cands, int64_t capacity, unsigned long long *count,
+                             void *stream) {
+  if (!plan) return set_error(FDAS_ERR_INVALID, "null plan");
+  if (!spectrum || !count) return set_error(FDAS_ERR_INVALID, "null spectrum or count pointer");
+  if (nbins < 1) return set_error(FDAS_ERR_INVALID, "nbins must be >= 1 (got %lld)", (long long)nbins);
+  if (capacity < 0 || (capacity > 0 && !cands))
+    return set_error(FDAS_ERR_INVALID, "need capacity >= 0 and a list when capacity > 0");
+  if (!std::isfinite(threshold)) return set_error(FDAS_ERR_INVALID, "threshold must be finite");
+  if ((reinterpret_cast<uintptr_t>(spectrum) & 7) || (reinterpret_cast<uintptr_t>(cands) & 15) ||
+      (reinterpret_cast<uintptr_t>(count) & 7))
+    return set_error(FDAS_ERR_INVALID, "misaligned spectrum, list or count pointer");
+  DeviceGuard guard(plan_device(plan));
+  if (guard.err != hipSuccess) return hip_error(guard.err, "hipSetDevice");
+  return plan_convolve_candidates(plan, spectrum, nbins, threshold, cands, capacity, count,
+                                  (hipStream_t)stream);
+}
+
 int fdas_convolve_batch(fdas_plan_t plan, const fdas_series *series, int nseries, void *stream) {
   if (!plan) return set_error(FDAS_ERR_INVALID, "null plan");
   if (!series || nseries < 1) return set_error(FDAS_ERR_INVALID, "need nseries >= 1 and a series array");

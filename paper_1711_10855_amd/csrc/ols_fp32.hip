@@ -156,7 +156,7 @@ __device__ __forceinline__ void ols_unit(const c32 *__restrict__ spec_, int64_t 
                                          const c32 *__restrict__ bank_, const c32 *__restrict__ tw_,
                                          float *__restrict__ power_, int64_t ld, int s, bool active,
                                          int U, int half, int z0, int z1, int row_base, c32 *buf0,
-                                         c32 *buf1, int &cur, int t) {
+                                         c32 *buf1, int &cur, int t, const CandOut &cd) {
   const auto spec = to_global(spec_);
   const auto bank = to_global(bank_);
   const auto tw = to_global(tw_);
@@ -269,7 +269,12 @@ __device__ __forceinline__ void ols_unit(const c32 *__restrict__ spec_, int64_t 
           const int64_t r = (int64_t)s * U + o - half;
           if (o >= half && o < half + U && r < nbins) {
             const c32 v = y[j * R0 + n];
-            __builtin_nontemporal_store(__builtin_fmaf(v.x, v.x, v.y * v.y), prow + r);
+            const float pw = __builtin_fmaf(v.x, v.x, v.y * v.y);
+            if (cd.count) {
+              if (pw >= cd.thr) cand_append(cd, iz - row_base, r, pw);
+            } else {
+              __builtin_nontemporal_store(pw, prow + r);
+            }
           }
         }
     }
@@ -282,7 +287,7 @@ template <class Gm, int G, bool TWREG, bool PF, int WPE>
 __global__ void __launch_bounds__(Gm::T *G) __attribute__((amdgpu_waves_per_eu(WPE)))
     ols_fp32_kernel(const c32 *__restrict__ spec, int64_t nbins, const c32 *__restrict__ bank,
                     const c32 *__restrict__ tw, float *__restrict__ power, int64_t ld, int nseg,
-                    int U, int half, int nz, int zpb, int nsb) {
+                    int U, int half, int nz, int zpb, int nsb, CandOut cand) {
   constexpr int T = Gm::T, NB = Gm::NBUF;
   __shared__ c32 lds[NB][G][Gm::LP];
   const int tid = threadIdx.x;
@@ -295,7 +300,7 @@ __global__ void __launch_bounds__(Gm::T *G) __attribute__((amdgpu_waves_per_eu(W
   const int z0 = zg * zpb;
   const int z1 = min(nz, z0 + zpb);
   ols_unit<Gm, TWREG, PF>(spec, nbins, bank, tw, power, ld, s, s < nseg, U, half, z0, z1, 0,
-                          lds[0][sg], lds[NB - 1][sg], cur, t);
+                          lds[0][sg], lds[NB - 1][sg], cur, t, cand);
 }
 
 // Batch: persistent blocks take work items (series, template group, segment
@@ -335,9 +340,10 @@ __global__ void __launch_bounds__(Gm::T *G) __attribute__((amdgpu_waves_per_eu(W
     const int s = sb * G + sg;
     const int z0 = d.row_off + zg * d.zpb;
     const int z1 = min(d.row_off + d.nz, z0 + d.zpb);
+    const CandOut none{};
     ols_unit<Gm, TWREG, PF>(static_cast<const c32 *>(d.spec), d.nbins, opaque_ptr(bank),
                             opaque_ptr(tw), d.power, d.ld, s, s < d.nseg, U, half, z0, z1,
-                            d.row_off, lds[0][sg], lds[NB - 1][sg], cur, t);
+                            d.row_off, lds[0][sg], lds[NB - 1][sg], cur, t, none);
   }
 }
 
@@ -371,12 +377,18 @@ __global__ void __launch_bounds__(Gm::T *G) __attribute__((amdgpu_waves_per_eu(W
   const int z0 = d.row_off + zg * d.zpb;
   const int z1 = min(d.row_off + d.nz, z0 + d.zpb);
   int cur = 0;
+  const CandOut none{};
   ols_unit<Gm, TWREG, PF>(static_cast<const c32 *>(d.spec), d.nbins, bank, tw, d.power, d.ld, s,
                           s < d.nseg, U, half, z0, z1, d.row_off, lds[0][sg], lds[NB - 1][sg],
-                          cur, t);
+                          cur, t, none);
 }
 
 __global__ void reset_counter_kernel(unsigned long long *counter) { *counter = 0ULL; }
+
+hipError_t launch_reset_counter(unsigned long long *counter, hipStream_t s) {
+  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, counter);
+  return hipGetLastError();
+}
 
 static bool batch_persistent() {
   const char *e = std::getenv("FDAS_BATCH_PERSISTENT");
@@ -393,7 +405,7 @@ static hipError_t launch_variant(const OlsArgs &a, hipStream_t st) {
   hipLaunchKernelGGL((ols_fp32_kernel<Gm, G, TWREG, PF, WPE>), dim3((unsigned)blocks),
                      dim3(Gm::T * G), 0, st, static_cast<const c32 *>(a.spec), a.nbins,
                      static_cast<const c32 *>(a.bank), static_cast<const c32 *>(a.tw), a.power,
-                     a.ld, a.nseg, a.U, a.half, a.nz, a.zpb, nsb);
+                     a.ld, a.nseg, a.U, a.half, a.nz, a.zpb, nsb, a.cand);
   return hipGetLastError();
 }
 

@@ -229,7 +229,7 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
                                            float *__restrict__ power_, int64_t ld, int s,
                                            bool active, int U, int half, int z0, int z1,
                                            int row_base, int bank_log2, unsigned char *smem,
-                                           float *s_max) {
+                                           float *s_max, const CandOut &cd) {
   typedef typename Vec<H>::v8 v8;
   constexpr int L = 4096;
   constexpr int TPW = 16 / NW;
@@ -384,6 +384,15 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
       const int o0 = 256 * blk + 4 * lane;
       const f4 v = *reinterpret_cast<const f4 *>(stg + 260 * blk + 4 * lane);
       const int64_t r0 = (int64_t)s * U + o0 - half;
+      if (cd.count) {  // detection epilogue instead of the plane
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int o = o0 + i;
+          if (o >= half && o < half + U && r0 + i < nbins && v[i] >= cd.thr)
+            cand_append(cd, izr - row_base, r0 + i, v[i]);
+        }
+        continue;
+      }
       if (o0 >= half && o0 + 3 < half + U && r0 + 3 < nbins &&
           ((reinterpret_cast<uintptr_t>(prow + r0) & 15) == 0)) {
         if constexpr (NT) __builtin_nontemporal_store(v, reinterpret_cast<gptr<f4>>(prow + r0));
@@ -472,7 +481,7 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(OC
     ols_mixed4096_kernel(const c32 *__restrict__ spec, int64_t nbins, const H *__restrict__ bank,
                          const c32 *__restrict__ tw, const unsigned char *__restrict__ consts,
                          float *__restrict__ power, int64_t ld, int nseg, int U, int half, int nz,
-                         int zpb, int nsb, int bank_log2) {
+                         int zpb, int nsb, int bank_log2, CandOut cand) {
   __shared__ __attribute__((aligned(16))) unsigned char smem[mix_smem<SPLIT>()];
   __shared__ float s_max[NW];
   const int sb = blockIdx.x % nsb;
@@ -480,7 +489,7 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(OC
   const int z0 = zg * zpb;
   const int z1 = min(nz, z0 + zpb);
   mixed_unit<H, PF, NT, NW, SPLIT>(consts, spec, nbins, bank, tw, power, ld, sb, sb < nseg, U, half, z0, z1,
-                            0, bank_log2, smem, s_max);
+                            0, bank_log2, smem, s_max, cand);
 }
 
 // Batched form as one flat launch: block b takes work item b (items are
@@ -509,8 +518,10 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(OC
   const int sb = (int)(local % d.nseg);
   const int z0 = d.row_off + zg * d.zpb;
   const int z1 = min(d.row_off + d.nz, z0 + d.zpb);
+  const CandOut none{};
   mixed_unit<H, PF, NT, NW, SPLIT>(consts, static_cast<const c32 *>(d.spec), d.nbins, bank, tw, d.power,
-                            d.ld, sb, true, U, half, z0, z1, d.row_off, bank_log2, smem, s_max);
+                            d.ld, sb, true, U, half, z0, z1, d.row_off, bank_log2, smem, s_max,
+                            none);
 }
 
 template <class H, bool PF, bool NT, int NW, int OCC, bool SPLIT>
@@ -522,7 +533,7 @@ static hipError_t launch_mixed4096(const OlsArgs &a, hipStream_t st) {
                      static_cast<const c32 *>(a.spec), a.nbins, static_cast<const H *>(a.bank),
                      static_cast<const c32 *>(a.tw),
                      static_cast<const unsigned char *>(a.consts), a.power, a.ld, a.nseg, a.U,
-                     a.half, a.nz, a.zpb, nsb, a.bank_log2);
+                     a.half, a.nz, a.zpb, nsb, a.bank_log2, a.cand);
   return hipGetLastError();
 }
 

@@ -10,6 +10,31 @@
 
 namespace fdas {
 
+// Detection epilogue: with `count` set, plane points whose power is at least
+// `thr` are counted on `count` and written to `list` while the slot is below
+// `cap` (list may be null when cap is 0), instead of the plane being stored.
+struct Cand {
+  int row;
+  float power;
+  int64_t r;
+};
+static_assert(sizeof(Cand) == 16, "candidate record is 16 bytes");
+struct CandOut {
+  Cand *list;
+  unsigned long long *count;
+  int64_t cap;
+  float thr;
+};
+
+__device__ __forceinline__ void cand_append(const CandOut &cd, int row, int64_t r, float p) {
+  typedef int i4v __attribute__((ext_vector_type(4)));
+  const unsigned long long i = atomicAdd(cd.count, 1ULL);
+  if (i < (unsigned long long)cd.cap) {
+    const i4v v = {row, __builtin_bit_cast(int, p), (int)(uint64_t)r, (int)((uint64_t)r >> 32)};
+    *(gptr<i4v>)(cd.list + i) = v;  // one 16-byte store
+  }
+}
+
 struct OlsArgs {
   const void *spec;  // complex64 [nbins]
   int64_t nbins;
@@ -24,6 +49,7 @@ struct OlsArgs {
   int zpb;           // templates per work unit
   int bank_log2;     // mixed precision: the bank is stored times 2^bank_log2
   const void *consts;  // mixed precision: per-lane constants table
+  CandOut cand;        // detection epilogue (count == nullptr: store the plane)
 };
 
 // One series of a batch as the persistent kernel sees it.
@@ -76,6 +102,7 @@ hipError_t launch_mixed_consts(void *out, int L, int precision, int split, hipSt
 hipError_t launch_bank_mixed_natural(c32 *dst, const void *bank, int nz, int L, int precision,
                                      int split, hipStream_t s);
 
+hipError_t launch_reset_counter(unsigned long long *counter, hipStream_t s);
 hipError_t launch_templates(void *out, int rows, int m, double zmax, double dz, int interbin,
                             hipStream_t s);
 hipError_t launch_twiddles(c32 *tw, int L, hipStream_t s);

@@ -402,8 +402,8 @@ static int launch_zpb(fdas_plan_t pl, int64_t nsb) {
   return best_zpb;
 }
 
-int plan_convolve(fdas_plan_t pl, const void *spec, int64_t nbins, float *power, int64_t ld,
-                  hipStream_t s) {
+static int plan_launch(fdas_plan_t pl, const void *spec, int64_t nbins, float *power, int64_t ld,
+                       const CandOut &cand, hipStream_t s) {
   const int64_t nseg = (nbins + pl->U - 1) / pl->U;
   if (nseg > INT_MAX / 2) return set_error(FDAS_ERR_UNSUPPORTED, "nbins %lld too large", (long long)nbins);
   const int64_t nsb = (nseg + pl->var->G - 1) / pl->var->G;
@@ -426,9 +426,30 @@ int plan_convolve(fdas_plan_t pl, const void *spec, int64_t nbins, float *power,
   a.bank_log2 = 0;
   while ((1 << a.bank_log2) < pl->L) ++a.bank_log2;
   a.consts = pl->consts;
+  a.cand = cand;
   hipError_t e = pl->var->launch(a, s);
   if (e != hipSuccess) return hip_error(e, "correlation kernel launch");
   return FDAS_OK;
+}
+
+int plan_convolve(fdas_plan_t pl, const void *spec, int64_t nbins, float *power, int64_t ld,
+                  hipStream_t s) {
+  return plan_launch(pl, spec, nbins, power, ld, CandOut{}, s);
+}
+
+// Detection epilogue: the count is cleared on the stream by a kernel (no
+// memset node, so the call may be captured), then the correlation kernel
+// appends every plane point with power >= thr.
+int plan_convolve_candidates(fdas_plan_t pl, const void *spec, int64_t nbins, float thr,
+                             void *cands, int64_t cap, unsigned long long *count, hipStream_t s) {
+  hipError_t e = launch_reset_counter(count, s);
+  if (e != hipSuccess) return hip_error(e, "candidate counter reset");
+  CandOut cd;
+  cd.list = static_cast<Cand *>(cands);
+  cd.count = count;
+  cd.cap = cap;
+  cd.thr = thr;
+  return plan_launch(pl, spec, nbins, nullptr, 0, cd, s);
 }
 
 // Host side of the batched path: validate and order the series (largest

@@ -35,6 +35,7 @@ EXPORTS = (
     "fdas_plane_rows", "fdas_resolve_params", "fdas_make_templates", "fdas_plan",
     "fdas_plan_get_info", "fdas_plan_bank", "fdas_convolve", "fdas_convolve_batch",
     "fdas_destroy", "fdas_status_string", "fdas_last_error", "fdas_kernel_variants",
+    "fdas_convolve_candidates",
 )
 
 
@@ -94,6 +95,9 @@ def load():
     lib.fdas_convolve.restype = C.c_int
     lib.fdas_convolve_batch.argtypes = [C.c_void_p, P(Series), C.c_int, C.c_void_p]
     lib.fdas_convolve_batch.restype = C.c_int
+    lib.fdas_convolve_candidates.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_float,
+                                             C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
+    lib.fdas_convolve_candidates.restype = C.c_int
     lib.fdas_destroy.argtypes = [C.c_void_p]
     lib.fdas_destroy.restype = C.c_int
     lib.fdas_status_string.argtypes = [C.c_int]
@@ -233,6 +237,30 @@ class Plan:
                "fdas_convolve")
         return out[:, :nbins] if out.shape[1] != nbins else out
 
+    def candidates(self, spectrum, threshold, capacity=1 << 16, buf=None):
+        """Detection epilogue: plane points with power >= threshold.
+
+        Returns (records, count): ``records`` is a device int64 tensor
+        [capacity, 2] holding fdas_candidate entries (decode with
+        ``decode_candidates``), ``count`` a one-element device int64 tensor
+        with the number of points found (records beyond capacity are
+        dropped). ``buf`` may pass both tensors back in to reuse them."""
+        import torch
+        if spectrum.dtype != torch.complex64 or not spectrum.is_cuda or spectrum.dim() != 1:
+            raise TypeError("spectrum must be a 1-D complex64 CUDA tensor")
+        spectrum = spectrum.contiguous()
+        if buf is None:
+            rec = torch.empty((capacity, 2), dtype=torch.int64, device=spectrum.device)
+            cnt = torch.empty(1, dtype=torch.int64, device=spectrum.device)
+        else:
+            rec, cnt = buf
+            capacity = rec.shape[0]
+        _check(self._lib.fdas_convolve_candidates(
+            self._h, C.c_void_p(spectrum.data_ptr()), spectrum.numel(), float(threshold),
+            C.c_void_p(rec.data_ptr()), capacity, C.c_void_p(cnt.data_ptr()),
+            _stream(spectrum.device)), "fdas_convolve_candidates")
+        return rec, cnt
+
     def convolve_batch(self, spectra, zmaxs, outs):
         """Batched form: one launch over every series (see fdas_convolve_batch)."""
         n = len(spectra)
@@ -260,6 +288,17 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def decode_candidates(rec, count):
+    """(row, r, power) numpy arrays from the tensors of Plan.candidates."""
+    import numpy as np
+    n = min(int(count.cpu()[0]), rec.shape[0])
+    raw = rec[:n].cpu().numpy()
+    lo = raw[:, 0].astype(np.uint64)
+    row = (lo & np.uint64(0xFFFFFFFF)).astype(np.uint32).view(np.int32)
+    power = (lo >> np.uint64(32)).astype(np.uint32).view(np.float32)
+    return row.astype(np.int64), raw[:, 1].copy(), power.astype(np.float32)
 
 
 def convolve(spectrum, zmax, dz, m=0, seg_len=0, precision="fp32", flags=0):

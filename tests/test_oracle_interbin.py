@@ -89,3 +89,22 @@ def test_planted_half_bin_mistakes_are_caught(shift):
     b = oracle.correlate_direct(a, wrong, m)[0, 3000]
     right = oracle.plane_direct(a, 0.0, 2.0, m, interbin=True)[1, 3000]
     assert abs(abs(b) ** 2 - right) > 0.05 * right
+
+
+def test_candidates_are_the_thresholded_plane():
+    """Candidates of unit-power complex Gaussian noise: P at each point is
+    exponential with mean E_w (the window's share of sum |H|^2), so the
+    expected count above t is N exp(-t / E_w); and a strong injected tone
+    is among them at its bin."""
+    n = 1 << 15
+    a = synth.small_random_spectrum(n, seed=77).astype(np.complex128)
+    m, t = 64, 7.0
+    row, r, p = oracle.candidates_direct(a, 16.0, 2.0, m, t)
+    assert np.all(p >= t) and np.all(np.diff(row * n + r) > 0)
+    _, h = oracle.templates64(16.0, 2.0, m)
+    ew = np.sum(np.abs(h) ** 2, axis=1)            # per row, <= 1
+    expect = float(np.sum(n * np.exp(-t / ew)))
+    assert 0.7 * expect < row.size < 1.3 * expect
+    tone = synth.noise_free_chirp_spectrum(1 << 16, synth.Chirp(3000.0, 0.0, 8.0, 0.2))
+    row2, r2, _ = oracle.candidates_direct(tone[:n], 16.0, 2.0, m, 30.0)
+    assert (8, 3000) in set(zip(row2.tolist(), r2.tolist()))   # z = 0 row
