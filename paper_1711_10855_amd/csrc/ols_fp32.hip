@@ -151,7 +151,7 @@ __device__ __forceinline__ void exchange(c32 (&d)[Gm::E], c32 *buf0, c32 *buf1, 
 
 // One work unit: segment s of a spectrum, bank rows [z0, z1), plane rows
 // (iz - row_base). `cur` carries the LDS buffer parity across units.
-template <class Gm, bool TWREG, bool PF>
+template <class Gm, bool TWREG, bool PF, bool CAND>
 __device__ __forceinline__ void ols_unit(const c32 *__restrict__ spec_, int64_t nbins,
                                          const c32 *__restrict__ bank_, const c32 *__restrict__ tw_,
                                          float *__restrict__ power_, int64_t ld, int s, bool active,
@@ -258,7 +258,22 @@ __device__ __forceinline__ void ols_unit(const c32 *__restrict__ spec_, int64_t 
     });
 
     // outputs: slot j*R0 + n holds index n * S0 + t + j T of the segment
-    if (active) {
+    if constexpr (CAND) {
+      // detection epilogue: every lane takes part in each offer (one atomic
+      // per wave that has a hit)
+      constexpr int S0 = Gm::S(0), R0 = Gm::R[0];
+#pragma unroll
+      for (int j = 0; j < Gm::B(0); ++j)
+#pragma unroll
+        for (int n = 0; n < R0; ++n) {
+          const int o = n * S0 + t + j * T;
+          const int64_t r = (int64_t)s * U + o - half;
+          const c32 v = y[j * R0 + n];
+          const float pw = __builtin_fmaf(v.x, v.x, v.y * v.y);
+          const bool hit = active && o >= half && o < half + U && r < nbins && pw >= cd.thr;
+          cand_offer(cd, hit, iz - row_base, r, pw);
+        }
+    } else if (active) {
       constexpr int S0 = Gm::S(0), R0 = Gm::R[0];
       const auto prow = power + (int64_t)(iz - row_base) * ld;
 #pragma unroll
@@ -269,12 +284,7 @@ __device__ __forceinline__ void ols_unit(const c32 *__restrict__ spec_, int64_t 
           const int64_t r = (int64_t)s * U + o - half;
           if (o >= half && o < half + U && r < nbins) {
             const c32 v = y[j * R0 + n];
-            const float pw = __builtin_fmaf(v.x, v.x, v.y * v.y);
-            if (cd.count) {
-              if (pw >= cd.thr) cand_append(cd, iz - row_base, r, pw);
-            } else {
-              __builtin_nontemporal_store(pw, prow + r);
-            }
+            __builtin_nontemporal_store(__builtin_fmaf(v.x, v.x, v.y * v.y), prow + r);
           }
         }
     }
@@ -283,7 +293,7 @@ __device__ __forceinline__ void ols_unit(const c32 *__restrict__ spec_, int64_t 
 
 // Single spectrum: block -> (segment group, template group), template-group
 // major so concurrently running blocks share bank rows in L2.
-template <class Gm, int G, bool TWREG, bool PF, int WPE>
+template <class Gm, int G, bool TWREG, bool PF, int WPE, bool CAND>
 __global__ void __launch_bounds__(Gm::T *G) __attribute__((amdgpu_waves_per_eu(WPE)))
     ols_fp32_kernel(const c32 *__restrict__ spec, int64_t nbins, const c32 *__restrict__ bank,
                     const c32 *__restrict__ tw, float *__restrict__ power, int64_t ld, int nseg,
@@ -299,7 +309,7 @@ __global__ void __launch_bounds__(Gm::T *G) __attribute__((amdgpu_waves_per_eu(W
   int cur = 0;
   const int z0 = zg * zpb;
   const int z1 = min(nz, z0 + zpb);
-  ols_unit<Gm, TWREG, PF>(spec, nbins, bank, tw, power, ld, s, s < nseg, U, half, z0, z1, 0,
+  ols_unit<Gm, TWREG, PF, CAND>(spec, nbins, bank, tw, power, ld, s, s < nseg, U, half, z0, z1, 0,
                           lds[0][sg], lds[NB - 1][sg], cur, t, cand);
 }
 
@@ -341,7 +351,7 @@ __global__ void __launch_bounds__(Gm::T *G) __attribute__((amdgpu_waves_per_eu(W
     const int z0 = d.row_off + zg * d.zpb;
     const int z1 = min(d.row_off + d.nz, z0 + d.zpb);
     const CandOut none{};
-    ols_unit<Gm, TWREG, PF>(static_cast<const c32 *>(d.spec), d.nbins, opaque_ptr(bank),
+    ols_unit<Gm, TWREG, PF, false>(static_cast<const c32 *>(d.spec), d.nbins, opaque_ptr(bank),
                             opaque_ptr(tw), d.power, d.ld, s, s < d.nseg, U, half, z0, z1,
                             d.row_off, lds[0][sg], lds[NB - 1][sg], cur, t, none);
   }
@@ -378,7 +388,7 @@ __global__ void __launch_bounds__(Gm::T *G) __attribute__((amdgpu_waves_per_eu(W
   const int z1 = min(d.row_off + d.nz, z0 + d.zpb);
   int cur = 0;
   const CandOut none{};
-  ols_unit<Gm, TWREG, PF>(static_cast<const c32 *>(d.spec), d.nbins, bank, tw, d.power, d.ld, s,
+  ols_unit<Gm, TWREG, PF, false>(static_cast<const c32 *>(d.spec), d.nbins, bank, tw, d.power, d.ld, s,
                           s < d.nseg, U, half, z0, z1, d.row_off, lds[0][sg], lds[NB - 1][sg],
                           cur, t, none);
 }
@@ -402,10 +412,16 @@ static hipError_t launch_variant(const OlsArgs &a, hipStream_t st) {
   const int nsb = (a.nseg + G - 1) / G;
   const int nzg = (a.nz + a.zpb - 1) / a.zpb;
   const long blocks = (long)nsb * nzg;
-  hipLaunchKernelGGL((ols_fp32_kernel<Gm, G, TWREG, PF, WPE>), dim3((unsigned)blocks),
-                     dim3(Gm::T * G), 0, st, static_cast<const c32 *>(a.spec), a.nbins,
-                     static_cast<const c32 *>(a.bank), static_cast<const c32 *>(a.tw), a.power,
-                     a.ld, a.nseg, a.U, a.half, a.nz, a.zpb, nsb, a.cand);
+  if (a.cand.count)
+    hipLaunchKernelGGL((ols_fp32_kernel<Gm, G, TWREG, PF, WPE, true>), dim3((unsigned)blocks),
+                       dim3(Gm::T * G), 0, st, static_cast<const c32 *>(a.spec), a.nbins,
+                       static_cast<const c32 *>(a.bank), static_cast<const c32 *>(a.tw), a.power,
+                       a.ld, a.nseg, a.U, a.half, a.nz, a.zpb, nsb, a.cand);
+  else
+    hipLaunchKernelGGL((ols_fp32_kernel<Gm, G, TWREG, PF, WPE, false>), dim3((unsigned)blocks),
+                       dim3(Gm::T * G), 0, st, static_cast<const c32 *>(a.spec), a.nbins,
+                       static_cast<const c32 *>(a.bank), static_cast<const c32 *>(a.tw), a.power,
+                       a.ld, a.nseg, a.U, a.half, a.nz, a.zpb, nsb, a.cand);
   return hipGetLastError();
 }
 
@@ -441,7 +457,7 @@ template <class Gm, int G, bool TWREG, bool PF, int WPE>
 static int grid_blocks_per_cu() {
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &nb, reinterpret_cast<const void *>(&ols_fp32_kernel<Gm, G, TWREG, PF, WPE>), Gm::T * G,
+          &nb, reinterpret_cast<const void *>(&ols_fp32_kernel<Gm, G, TWREG, PF, WPE, false>), Gm::T * G,
           0) != hipSuccess)
     return 0;
   return nb;

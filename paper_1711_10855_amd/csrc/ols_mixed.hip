@@ -222,7 +222,7 @@ __device__ __forceinline__ void load_mixed_consts(MixedConsts<H, NW, SPLIT> &K,
 
 // One work unit of the mixed kernel: segment s, bank rows [z0, z1), plane
 // rows iz - row_base. Every thread of the block calls it (barriers inside).
-template <class H, bool PF, bool NT, int NW, bool SPLIT>
+template <class H, bool PF, bool NT, int NW, bool SPLIT, bool CAND>
 __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ consts_,
                                            const c32 *__restrict__ spec_, int64_t nbins,
                                            const H *__restrict__ bank_, const c32 *__restrict__ tw_,
@@ -376,7 +376,7 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
   // barrier wave w stores outputs [256 TPW w, 256 TPW (w + 1)) of the
   // segment, 1 KB contiguous per store instruction.
   auto store_staged = [&](int izr) {
-    if (!active) return;
+    if (!CAND && !active) return;
     const auto prow = power + (int64_t)(izr - row_base) * ld;
 #pragma unroll
     for (int q = 0; q < TPW; ++q) {
@@ -384,12 +384,12 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
       const int o0 = 256 * blk + 4 * lane;
       const f4 v = *reinterpret_cast<const f4 *>(stg + 260 * blk + 4 * lane);
       const int64_t r0 = (int64_t)s * U + o0 - half;
-      if (cd.count) {  // detection epilogue instead of the plane
+      if constexpr (CAND) {  // detection epilogue instead of the plane (all lanes offer)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int o = o0 + i;
-          if (o >= half && o < half + U && r0 + i < nbins && v[i] >= cd.thr)
-            cand_append(cd, izr - row_base, r0 + i, v[i]);
+          const bool hit = active && o >= half && o < half + U && r0 + i < nbins && v[i] >= cd.thr;
+          cand_offer(cd, hit, izr - row_base, r0 + i, v[i]);
         }
         continue;
       }
@@ -476,7 +476,7 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
   }
 }
 
-template <class H, bool PF, bool NT, int NW, int OCC, bool SPLIT>
+template <class H, bool PF, bool NT, int NW, int OCC, bool SPLIT, bool CAND>
 __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(OCC, OCC)))
     ols_mixed4096_kernel(const c32 *__restrict__ spec, int64_t nbins, const H *__restrict__ bank,
                          const c32 *__restrict__ tw, const unsigned char *__restrict__ consts,
@@ -488,8 +488,8 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(OC
   const int zg = blockIdx.x / nsb;
   const int z0 = zg * zpb;
   const int z1 = min(nz, z0 + zpb);
-  mixed_unit<H, PF, NT, NW, SPLIT>(consts, spec, nbins, bank, tw, power, ld, sb, sb < nseg, U, half, z0, z1,
-                            0, bank_log2, smem, s_max, cand);
+  mixed_unit<H, PF, NT, NW, SPLIT, CAND>(consts, spec, nbins, bank, tw, power, ld, sb, sb < nseg,
+                                         U, half, z0, z1, 0, bank_log2, smem, s_max, cand);
 }
 
 // Batched form as one flat launch: block b takes work item b (items are
@@ -519,7 +519,7 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(OC
   const int z0 = d.row_off + zg * d.zpb;
   const int z1 = min(d.row_off + d.nz, z0 + d.zpb);
   const CandOut none{};
-  mixed_unit<H, PF, NT, NW, SPLIT>(consts, static_cast<const c32 *>(d.spec), d.nbins, bank, tw, d.power,
+  mixed_unit<H, PF, NT, NW, SPLIT, false>(consts, static_cast<const c32 *>(d.spec), d.nbins, bank, tw, d.power,
                             d.ld, sb, true, U, half, z0, z1, d.row_off, bank_log2, smem, s_max,
                             none);
 }
@@ -529,11 +529,18 @@ static hipError_t launch_mixed4096(const OlsArgs &a, hipStream_t st) {
   const int nsb = a.nseg;
   const int nzg = (a.nz + a.zpb - 1) / a.zpb;
   const long blocks = (long)nsb * nzg;
-  hipLaunchKernelGGL((ols_mixed4096_kernel<H, PF, NT, NW, OCC, SPLIT>), dim3((unsigned)blocks), dim3(64 * NW), 0, st,
-                     static_cast<const c32 *>(a.spec), a.nbins, static_cast<const H *>(a.bank),
-                     static_cast<const c32 *>(a.tw),
-                     static_cast<const unsigned char *>(a.consts), a.power, a.ld, a.nseg, a.U,
-                     a.half, a.nz, a.zpb, nsb, a.bank_log2, a.cand);
+  if (a.cand.count)
+    hipLaunchKernelGGL((ols_mixed4096_kernel<H, PF, NT, NW, OCC, SPLIT, true>), dim3((unsigned)blocks),
+                       dim3(64 * NW), 0, st, static_cast<const c32 *>(a.spec), a.nbins,
+                       static_cast<const H *>(a.bank), static_cast<const c32 *>(a.tw),
+                       static_cast<const unsigned char *>(a.consts), a.power, a.ld, a.nseg, a.U,
+                       a.half, a.nz, a.zpb, nsb, a.bank_log2, a.cand);
+  else
+    hipLaunchKernelGGL((ols_mixed4096_kernel<H, PF, NT, NW, OCC, SPLIT, false>), dim3((unsigned)blocks),
+                       dim3(64 * NW), 0, st, static_cast<const c32 *>(a.spec), a.nbins,
+                       static_cast<const H *>(a.bank), static_cast<const c32 *>(a.tw),
+                       static_cast<const unsigned char *>(a.consts), a.power, a.ld, a.nseg, a.U,
+                       a.half, a.nz, a.zpb, nsb, a.bank_log2, a.cand);
   return hipGetLastError();
 }
 
@@ -556,7 +563,7 @@ template <class H, bool PF, bool NT, int NW, int OCC, bool SPLIT>
 static int mixed_grid_blocks_per_cu() {
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &nb, reinterpret_cast<const void *>(&ols_mixed4096_kernel<H, PF, NT, NW, OCC, SPLIT>), 64 * NW,
+          &nb, reinterpret_cast<const void *>(&ols_mixed4096_kernel<H, PF, NT, NW, OCC, SPLIT, false>), 64 * NW,
           0) != hipSuccess)
     return 0;
   return nb;

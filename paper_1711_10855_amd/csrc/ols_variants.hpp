@@ -26,12 +26,28 @@ struct CandOut {
   float thr;
 };
 
-__device__ __forceinline__ void cand_append(const CandOut &cd, int row, int64_t r, float p) {
+// Called by every lane of the wave together (not under divergent control
+// flow); lanes with `hit` set append (row, r, p). One atomic per wave that has
+// any hit: lanes take consecutive slots in lane order.
+__device__ __forceinline__ void cand_offer(const CandOut &cd, bool hit, int row, int64_t r,
+                                           float p) {
   typedef int i4v __attribute__((ext_vector_type(4)));
-  const unsigned long long i = atomicAdd(cd.count, 1ULL);
-  if (i < (unsigned long long)cd.cap) {
-    const i4v v = {row, __builtin_bit_cast(int, p), (int)(uint64_t)r, (int)((uint64_t)r >> 32)};
-    *(gptr<i4v>)(cd.list + i) = v;  // one 16-byte store
+  const unsigned long long mask = __builtin_amdgcn_ballot_w64(hit);
+  if (mask == 0ull) return;
+  const int lane = (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+  const int first = __builtin_ctzll(mask);
+  unsigned long long base = 0ull;
+  if (lane == first) base = atomicAdd(cd.count, (unsigned long long)__builtin_popcountll(mask));
+  const unsigned lo = __builtin_amdgcn_readlane((unsigned)base, first);
+  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(base >> 32), first);
+  base = ((unsigned long long)hi << 32) | lo;
+  if (hit) {
+    const unsigned long long i =
+        base + (unsigned long long)__builtin_popcountll(mask & ((1ull << lane) - 1ull));
+    if (i < (unsigned long long)cd.cap) {
+      const i4v v = {row, __builtin_bit_cast(int, p), (int)(uint64_t)r, (int)((uint64_t)r >> 32)};
+      *(gptr<i4v>)(cd.list + i) = v;  // one 16-byte store
+    }
   }
 }
 
