@@ -118,15 +118,17 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // Registers in the layout of stage A -> LDS -> registers in the layout of
-// stage Bst. Block-wide exchanges flip the buffer so that one barrier per
-// exchange suffices; wave-local exchanges touch only addresses their own
-// wave owns and use the buffer of the next block-wide exchange.
-template <class Gm, int A, int Bst>
-__device__ __forceinline__ void exchange(c32 (&d)[Gm::E], c32 *buf0, c32 *buf1, int &cur, int t) {
+// stage Bst, through buffer PAR. Block-wide exchanges alternate between the
+// two buffers so that one barrier per exchange suffices; wave-local exchanges
+// touch only addresses their own wave owns and use the buffer of the next
+// block-wide exchange. The parity is a compile-time value, so every LDS
+// address is a loop-invariant register plus an immediate offset.
+template <class Gm, int A, int Bst, int PAR>
+__device__ __forceinline__ void exchange(c32 (&d)[Gm::E], c32 *buf0, c32 *buf1, int t) {
   constexpr int RA = Gm::R[A], RB = Gm::R[Bst];
   constexpr int lo = A < Bst ? A : Bst;
   constexpr bool loc = Gm::local(lo);
-  c32 *buf = cur ? buf1 : buf0;
+  c32 *buf = PAR ? buf1 : buf0;
 #pragma unroll
   for (int j = 0; j < Gm::B(A); ++j)
 #pragma unroll
@@ -142,21 +144,30 @@ __device__ __forceinline__ void exchange(c32 (&d)[Gm::E], c32 *buf0, c32 *buf1, 
     for (int n = 0; n < RB; ++n) d[j * RB + n] = buf[pad<Gm>(stage_addr<Gm, Bst>(t, j, n))];
   if constexpr (loc) {
     wave_sync();
-  } else if constexpr (Gm::NBUF == 2) {
-    cur ^= 1;
-  } else {
+  } else if constexpr (Gm::NBUF == 1) {
     __syncthreads();  // single buffer: every read done before the next write
   }
 }
 
+// Buffer parity bookkeeping: the number of block-wide exchanges among the
+// exchanges with lower stage index in [a, b) (each flips the buffer when
+// there are two).
+template <class Gm>
+constexpr int flips(int a, int b) {
+  int f = 0;
+  for (int j = a; j < b; ++j) f += (Gm::NBUF == 2 && !Gm::local(j)) ? 1 : 0;
+  return f;
+}
+
 // One work unit: segment s of a spectrum, bank rows [z0, z1), plane rows
-// (iz - row_base). `cur` carries the LDS buffer parity across units.
+// (iz - row_base). The unit starts on LDS buffer 0: its caller guarantees a
+// block barrier since any earlier unit's last LDS read.
 template <class Gm, bool TWREG, bool PF, bool CAND>
 __device__ __forceinline__ void ols_unit(const c32 *__restrict__ spec_, int64_t nbins,
                                          const c32 *__restrict__ bank_, const c32 *__restrict__ tw_,
                                          float *__restrict__ power_, int64_t ld, int s, bool active,
                                          int U, int half, int z0, int z1, int row_base, c32 *buf0,
-                                         c32 *buf1, int &cur, int t, const CandOut &cd) {
+                                         c32 *buf1, int t, const CandOut &cd) {
   const auto spec = to_global(spec_);
   const auto bank = to_global(bank_);
   const auto tw = to_global(tw_);
@@ -189,7 +200,7 @@ __device__ __forceinline__ void ols_unit(const c32 *__restrict__ spec_, int64_t 
   static_for_up<0, P>([&](auto ic) {
     constexpr int I = decltype(ic)::value;
     constexpr int R = Gm::R[I];
-    if constexpr (I > 0) exchange<Gm, I - 1, I>(x, buf0, buf1, cur, t);
+    if constexpr (I > 0) exchange<Gm, I - 1, I, flips<Gm>(0, I - 1) & 1>(x, buf0, buf1, t);
 #pragma unroll
     for (int j = 0; j < Gm::B(I); ++j) {
       dft<-1, R>(&x[j * R]);
@@ -219,16 +230,19 @@ __device__ __forceinline__ void ols_unit(const c32 *__restrict__ spec_, int64_t 
     });
   }
 
-  for (int iz = z0; iz < z1; ++iz) {
+  // one template; P0 is the buffer parity at its start
+  auto one = [&](int iz, auto p0c) {
+    constexpr int P0 = decltype(p0c)::value;
     c32 y[E];
     if constexpr (PF) {
 #pragma unroll
       for (int e = 0; e < E; ++e) y[e] = cmul(x[e], bnext[e]);
-      if (iz + 1 < z1) {
-        const auto brow = bank + (int64_t)(iz + 1) * L + t;
+      // the last template reloads its own row: an unconditional load keeps
+      // one register set for the bank (a conditional one makes the compiler
+      // copy the prefetched values across the loop edge)
+      const auto brow = bank + (int64_t)(iz + 1 < z1 ? iz + 1 : iz) * L + t;
 #pragma unroll
-        for (int e = 0; e < E; ++e) bnext[e] = ldg(brow + e * T);
-      }
+      for (int e = 0; e < E; ++e) bnext[e] = ldg(brow + e * T);
     } else {
       const auto brow = bank + (int64_t)iz * L + t;
 #pragma unroll
@@ -240,7 +254,7 @@ __device__ __forceinline__ void ols_unit(const c32 *__restrict__ spec_, int64_t 
       constexpr int I = decltype(ic)::value;
       constexpr int R = Gm::R[I];
       if constexpr (I < P - 1) {
-        exchange<Gm, I + 1, I>(y, buf0, buf1, cur, t);
+        exchange<Gm, I + 1, I, (P0 + flips<Gm>(I + 1, P - 1)) & 1>(y, buf0, buf1, t);
         constexpr int N = R * Gm::S(I);
 #pragma unroll
         for (int j = 0; j < Gm::B(I); ++j) {
@@ -288,6 +302,18 @@ __device__ __forceinline__ void ols_unit(const c32 *__restrict__ spec_, int64_t 
           }
         }
     }
+  };
+  constexpr int PF0 = flips<Gm>(0, P - 1) & 1;  // after the forward transform
+  if constexpr ((flips<Gm>(0, P - 1) & 1) == 0) {
+    for (int iz = z0; iz < z1; ++iz) one(iz, std::integral_constant<int, PF0>{});
+  } else {
+    // an odd number of flips per template: alternate the two parities
+    int iz = z0;
+    for (; iz + 1 < z1; iz += 2) {
+      one(iz, std::integral_constant<int, PF0>{});
+      one(iz + 1, std::integral_constant<int, PF0 ^ 1>{});
+    }
+    if (iz < z1) one(iz, std::integral_constant<int, PF0>{});
   }
 }
 
@@ -306,11 +332,10 @@ __global__ void __launch_bounds__(Gm::T *G) __attribute__((amdgpu_waves_per_eu(W
   const int sb = blockIdx.x % nsb;
   const int zg = blockIdx.x / nsb;
   const int s = sb * G + sg;
-  int cur = 0;
   const int z0 = zg * zpb;
   const int z1 = min(nz, z0 + zpb);
   ols_unit<Gm, TWREG, PF, CAND>(spec, nbins, bank, tw, power, ld, s, s < nseg, U, half, z0, z1, 0,
-                          lds[0][sg], lds[NB - 1][sg], cur, t, cand);
+                          lds[0][sg], lds[NB - 1][sg], t, cand);
 }
 
 // Batch: persistent blocks take work items (series, template group, segment
@@ -328,7 +353,7 @@ __global__ void __launch_bounds__(Gm::T *G) __attribute__((amdgpu_waves_per_eu(W
   const int tid = threadIdx.x;
   const int sg = tid / T;
   const int t = tid % T;
-  int cur = 0, par = 0;
+  int par = 0;
   for (;;) {
     if (tid == 0) s_item[par] = (long long)atomicAdd(counter, 1ULL);
     __syncthreads();
@@ -353,7 +378,7 @@ __global__ void __launch_bounds__(Gm::T *G) __attribute__((amdgpu_waves_per_eu(W
     const CandOut none{};
     ols_unit<Gm, TWREG, PF, false>(static_cast<const c32 *>(d.spec), d.nbins, opaque_ptr(bank),
                             opaque_ptr(tw), d.power, d.ld, s, s < d.nseg, U, half, z0, z1,
-                            d.row_off, lds[0][sg], lds[NB - 1][sg], cur, t, none);
+                            d.row_off, lds[0][sg], lds[NB - 1][sg], t, none);
   }
 }
 
@@ -386,11 +411,10 @@ __global__ void __launch_bounds__(Gm::T *G) __attribute__((amdgpu_waves_per_eu(W
   const int s = sb * G + sg;
   const int z0 = d.row_off + zg * d.zpb;
   const int z1 = min(d.row_off + d.nz, z0 + d.zpb);
-  int cur = 0;
   const CandOut none{};
   ols_unit<Gm, TWREG, PF, false>(static_cast<const c32 *>(d.spec), d.nbins, bank, tw, d.power, d.ld, s,
                           s < d.nseg, U, half, z0, z1, d.row_off, lds[0][sg], lds[NB - 1][sg],
-                          cur, t, none);
+                          t, none);
 }
 
 __global__ void reset_counter_kernel(unsigned long long *counter) { *counter = 0ULL; }
@@ -487,6 +511,7 @@ static constexpr OlsVariant make_variant(const char *name) {
 
 // Name: fp32_L<len>_t<threads per segment>[x<segments per block>]_r<radices>
 //       [_tg: twiddles re-read from the table | _np: no bank prefetch]
+//       [_o<n>: registers capped for n waves per SIMD]
 static const OlsVariant kFp32Variants[] = {
     // the first entry for each length is the default for that length
     make_variant<Geo<256, 32, 4, 8, 8>, 2, true, true, 4>("fp32_L256_t32x2_r4.8.8"),
@@ -495,12 +520,17 @@ static const OlsVariant kFp32Variants[] = {
     make_variant<Geo<512, 32, 2, 16, 16>, 2, false, true>("fp32_L512_t32x2_r2.16.16_tg"),
     make_variant<Geo<1024, 64, 4, 16, 16>, 1, false, true>("fp32_L1024_t64_r4.16.16_tg"),
     make_variant<Geo<1024, 128, 2, 8, 8, 8>, 1, true, true, 4>("fp32_L1024_t128_r2.8.8.8"),
-    make_variant<Geo<2048, 128, 8, 16, 16>, 1, false, true>("fp32_L2048_t128_r8.16.16_tg"),
+    make_variant<Geo<1024, 128, 2, 8, 8, 8>, 1, true, true, 3>("fp32_L1024_t128_r2.8.8.8_o3"),
+    make_variant<Geo<2048, 128, 8, 16, 16>, 1, true, true, 2>("fp32_L2048_t128_r8.16.16_o2"),
     make_variant<Geo<2048, 128, 8, 16, 16>, 1, true, false>("fp32_L2048_t128_r8.16.16_np"),
+    make_variant<Geo<2048, 128, 8, 16, 16>, 1, false, true, 2>("fp32_L2048_t128_r8.16.16_tg_o2"),
     make_variant<Geo<2048, 256, 4, 8, 8, 8>, 1, true, true, 3>("fp32_L2048_t256_r4.8.8.8"),
     make_variant<Geo<2048, 256, 4, 8, 8, 8>, 1, false, true, 3>("fp32_L2048_t256_r4.8.8.8_tg"),
-    make_variant<Geo<4096, 256, 16, 16, 16>, 1, false, true>("fp32_L4096_t256_r16.16.16_tg"),
+    make_variant<Geo<4096, 256, 16, 16, 16>, 1, true, true, 2>("fp32_L4096_t256_r16.16.16_o2"),
+    make_variant<Geo<4096, 256, 16, 16, 16>, 1, true, false, 2>("fp32_L4096_t256_r16.16.16_np"),
+    make_variant<Geo<4096, 256, 16, 16, 16>, 1, false, true, 2>("fp32_L4096_t256_r16.16.16_tg_o2"),
     make_variant<Geo<4096, 512, 8, 8, 8, 8>, 1, false, true>("fp32_L4096_t512_r8.8.8.8_tg"),
+    make_variant<Geo<4096, 512, 8, 8, 8, 8>, 1, true, true, 2>("fp32_L4096_t512_r8.8.8.8_o2"),
     make_variant<Geo<8192, 512, 2, 16, 16, 16>, 1, false, true>("fp32_L8192_t512_r2.16.16.16_tg"),
     make_variant<Geo<8192, 1024, 2, 8, 8, 8, 8>, 1, false, true>("fp32_L8192_t1024_r2.8.8.8.8_tg"),
     make_variant<Geo<16384, 1024, 4, 16, 16, 16>, 1, false, false>("fp32_L16384_t1024_r4.16.16.16_tg"),
