@@ -210,6 +210,41 @@ int fdas_destroy(fdas_plan_t plan);
  * variable; FDAS_ZPB overrides templates per work unit.                     */
 int fdas_kernel_variants(int seg_len, int precision, char *buf, size_t len);
 
+/* ---- standalone batched FFT ---------------------------------------------
+ * The shared-memory FFT the correlation kernel is built from, on its own
+ * (the FFT the paper measures separately, Section 3 and Table 1): batch
+ * transforms of length n, each held in registers and LDS by one group of
+ * threads with elems_per_thread elements per thread.
+ *   out[b][k] = sum_j in[b][j] exp(direction * 2 pi i j k / n)
+ * direction -1 is the forward transform of eq. 3, +1 the inverse (no 1/n).
+ * Buffers are device complex64 [batch][n], natural order, 8-byte aligned;
+ * in == out (in place) is allowed, other overlap is not.                    */
+typedef struct fdas_fft_s *fdas_fft_t;
+
+typedef struct {
+  int n;                    /* transform length                              */
+  int elems_per_thread;
+  int threads;              /* threads per transform                          */
+  int transforms_per_block;
+  char kernel[64];          /* compiled form                                  */
+} fdas_fft_info;
+
+/* Choose the compiled form for n (a power of two) and elems_per_thread (0 =
+ * the default for n) and build its FP64-generated twiddle table on `device`
+ * (allocates n * 8 bytes; synchronises `stream`). FDAS_ERR_UNSUPPORTED when
+ * no form of that length / elements per thread is compiled.                 */
+int fdas_fft_plan(fdas_fft_t *out, int n, int elems_per_thread, int device, void *stream);
+int fdas_fft_get_info(fdas_fft_t plan, fdas_fft_info *info);
+/* batch >= 0 transforms (0 is a no-op); asynchronous on `stream`, one kernel
+ * launch, no allocation.                                                     */
+int fdas_fft_exec(fdas_fft_t plan, const void *in, void *out, int64_t batch, int direction,
+                  void *stream);
+/* NULL is allowed. Synchronises the plan's device.                          */
+int fdas_fft_destroy(fdas_fft_t plan);
+/* Names of the compiled FFT forms of length n (0 = all), as for
+ * fdas_kernel_variants.                                                      */
+int fdas_fft_variants(int n, char *buf, size_t len);
+
 /* Static description of a status code.                                      */
 const char *fdas_status_string(int status);
 

@@ -14,6 +14,8 @@ Acceleration of the GPU Fourier Domain Acceleration Search Algorithm"):
 * ``correlate``  -- the matched-filter sum of eq. 2 (Section 1) evaluated
   directly, and, independently, the same result by overlap-and-save
   (Section 2) with naive DFT matrices built from eq. 3.
+* ``fft``        -- the unnormalised DFT of eq. 3 in both directions, for the
+  standalone batched FFT.
 """
 
 from .templates import (  # noqa: F401
@@ -34,3 +36,4 @@ from .correlate import (  # noqa: F401
     bank_natural,
     candidates_direct,
 )
+from .fft import dft_naive, dft64  # noqa: F401

@@ -8,9 +8,11 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <new>
 #include <string>
 
 #include "fdas.h"
+#include "fft_batch.hpp"
 #include "ols_variants.hpp"
 #include "plan.hpp"
 
@@ -113,6 +115,35 @@ struct DeviceGuard {
     if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
   }
 };
+
+}  // namespace fdas
+
+// Standalone batched FFT: the compiled form and its twiddle table.
+struct fdas_fft_s {
+  int device;
+  const fdas::FftVariant *v;
+  fdas::c32 *tw;
+};
+
+namespace fdas {
+
+// Compiled form for (n, elements per thread); elems 0 picks the default.
+static int find_fft(int n, int elems, const FftVariant **out) {
+  int count = 0;
+  const FftVariant *vs = fft_variants(&count);
+  bool length_known = false;
+  for (int i = 0; i < count; ++i) {
+    if (vs[i].L != n) continue;
+    length_known = true;
+    if (elems == 0 || vs[i].E == elems) {
+      *out = &vs[i];
+      return FDAS_OK;
+    }
+  }
+  if (!length_known) return set_error(FDAS_ERR_UNSUPPORTED, "no compiled FFT of length %d", n);
+  return set_error(FDAS_ERR_UNSUPPORTED, "no compiled FFT of length %d with %d elements per thread",
+                   n, elems);
+}
 
 }  // namespace fdas
 
@@ -257,6 +288,103 @@ int fdas_destroy(fdas_plan_t plan) {
   if (!plan) return FDAS_OK;
   DeviceGuard guard(plan_device(plan));
   return destroy_plan(plan);
+}
+
+int fdas_fft_plan(fdas_fft_t *out, int n, int elems_per_thread, int device, void *stream) {
+  if (!out) return set_error(FDAS_ERR_INVALID, "null plan pointer");
+  *out = nullptr;
+  if (n < 2 || (n & (n - 1)))
+    return set_error(FDAS_ERR_INVALID, "FFT length %d is not a power of two >= 2", n);
+  if (elems_per_thread < 0 || (elems_per_thread & (elems_per_thread - 1)))
+    return set_error(FDAS_ERR_INVALID, "elements per thread %d is not 0 or a power of two",
+                     elems_per_thread);
+  if (device < 0) return set_error(FDAS_ERR_INVALID, "device %d < 0", device);
+  const FftVariant *v = nullptr;
+  const int st = find_fft(n, elems_per_thread, &v);
+  if (st != FDAS_OK) return st;
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess) return hip_error(e, "hipGetDeviceCount");
+  if (device >= ndev) return set_error(FDAS_ERR_INVALID, "device %d of %d", device, ndev);
+  DeviceGuard guard(device);
+  if (guard.err != hipSuccess) return hip_error(guard.err, "hipSetDevice");
+  auto *p = new (std::nothrow) fdas_fft_s{device, v, nullptr};
+  if (!p) return set_error(FDAS_ERR_NOMEM, "host allocation");
+  e = hipMalloc(&p->tw, (size_t)n * sizeof(c32));
+  if (e != hipSuccess) {
+    delete p;
+    return set_error(FDAS_ERR_NOMEM, "twiddle table: %s", hipGetErrorString(e));
+  }
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  e = launch_twiddles(p->tw, n, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    (void)hipFree(p->tw);
+    delete p;
+    return hip_error(e, "twiddle table");
+  }
+  *out = p;
+  return FDAS_OK;
+}
+
+int fdas_fft_get_info(fdas_fft_t plan, fdas_fft_info *info) {
+  if (!plan || !info) return set_error(FDAS_ERR_INVALID, "null plan or info");
+  info->n = plan->v->L;
+  info->elems_per_thread = plan->v->E;
+  info->threads = plan->v->T;
+  info->transforms_per_block = plan->v->G;
+  std::snprintf(info->kernel, sizeof(info->kernel), "%s", plan->v->name);
+  return FDAS_OK;
+}
+
+int fdas_fft_exec(fdas_fft_t plan, const void *in, void *out, int64_t batch, int direction,
+                  void *stream) {
+  if (!plan) return set_error(FDAS_ERR_INVALID, "null plan");
+  if (direction != -1 && direction != 1)
+    return set_error(FDAS_ERR_INVALID, "direction %d is not -1 or +1", direction);
+  if (batch < 0) return set_error(FDAS_ERR_INVALID, "batch %lld < 0", (long long)batch);
+  if (batch == 0) return FDAS_OK;
+  if (!in || !out) return set_error(FDAS_ERR_INVALID, "null sample buffer");
+  if (reinterpret_cast<uintptr_t>(in) % 8 || reinterpret_cast<uintptr_t>(out) % 8)
+    return set_error(FDAS_ERR_INVALID, "sample buffers must be 8-byte aligned");
+  const int64_t blocks = (batch + plan->v->G - 1) / plan->v->G;
+  if (blocks > (int64_t)INT_MAX || batch > INT64_MAX / plan->v->L)
+    return set_error(FDAS_ERR_INVALID, "batch %lld too large", (long long)batch);
+  DeviceGuard guard(plan->device);
+  if (guard.err != hipSuccess) return hip_error(guard.err, "hipSetDevice");
+  const hipError_t e = plan->v->launch(in, out, batch, direction, plan->tw,
+                                       static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? FDAS_OK : hip_error(e, "FFT launch");
+}
+
+int fdas_fft_destroy(fdas_fft_t plan) {
+  if (!plan) return FDAS_OK;
+  DeviceGuard guard(plan->device);
+  hipError_t e = hipDeviceSynchronize();
+  const hipError_t f = hipFree(plan->tw);
+  delete plan;
+  if (e == hipSuccess) e = f;
+  return e == hipSuccess ? FDAS_OK : hip_error(e, "fdas_fft_destroy");
+}
+
+int fdas_fft_variants(int n, char *buf, size_t len) {
+  if (n < 0) return set_error(FDAS_ERR_INVALID, "length %d < 0", n);
+  if (!buf && len) return set_error(FDAS_ERR_INVALID, "null buffer with nonzero length");
+  int count = 0;
+  const FftVariant *vs = fft_variants(&count);
+  std::string all;
+  int k = 0;
+  for (int i = 0; i < count; ++i) {
+    if (n && vs[i].L != n) continue;
+    if (k++) all += "\n";
+    all += vs[i].name;
+  }
+  if (len) {
+    const size_t c = all.size() < len - 1 ? all.size() : len - 1;
+    std::memcpy(buf, all.data(), c);
+    buf[c] = 0;
+  }
+  return k;
 }
 
 }  // extern "C"

@@ -35,7 +35,8 @@ EXPORTS = (
     "fdas_plane_rows", "fdas_resolve_params", "fdas_make_templates", "fdas_plan",
     "fdas_plan_get_info", "fdas_plan_bank", "fdas_convolve", "fdas_convolve_batch",
     "fdas_destroy", "fdas_status_string", "fdas_last_error", "fdas_kernel_variants",
-    "fdas_convolve_candidates",
+    "fdas_convolve_candidates", "fdas_fft_plan", "fdas_fft_get_info", "fdas_fft_exec",
+    "fdas_fft_destroy", "fdas_fft_variants",
 )
 
 
@@ -54,6 +55,11 @@ class PlanInfo(C.Structure):
                 ("precision", C.c_int), ("flags", C.c_uint), ("threads", C.c_int),
                 ("templates_per_block", C.c_int), ("segments_per_block", C.c_int),
                 ("bank_bytes", C.c_size_t), ("plan_ms", C.c_double), ("kernel", C.c_char * 64)]
+
+
+class FftInfoC(C.Structure):
+    _fields_ = [("n", C.c_int), ("elems_per_thread", C.c_int), ("threads", C.c_int),
+                ("transforms_per_block", C.c_int), ("kernel", C.c_char * 64)]
 
 
 class FdasError(RuntimeError):
@@ -104,6 +110,17 @@ def load():
     lib.fdas_status_string.restype = C.c_char_p
     lib.fdas_kernel_variants.argtypes = [C.c_int, C.c_int, C.c_char_p, C.c_size_t]
     lib.fdas_kernel_variants.restype = C.c_int
+    lib.fdas_fft_plan.argtypes = [P(C.c_void_p), C.c_int, C.c_int, C.c_int, C.c_void_p]
+    lib.fdas_fft_plan.restype = C.c_int
+    lib.fdas_fft_get_info.argtypes = [C.c_void_p, P(FftInfoC)]
+    lib.fdas_fft_get_info.restype = C.c_int
+    lib.fdas_fft_exec.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int,
+                                  C.c_void_p]
+    lib.fdas_fft_exec.restype = C.c_int
+    lib.fdas_fft_destroy.argtypes = [C.c_void_p]
+    lib.fdas_fft_destroy.restype = C.c_int
+    lib.fdas_fft_variants.argtypes = [C.c_int, C.c_char_p, C.c_size_t]
+    lib.fdas_fft_variants.restype = C.c_int
     lib.fdas_last_error.argtypes = []
     lib.fdas_last_error.restype = C.c_char_p
     _lib = lib
@@ -299,6 +316,67 @@ def decode_candidates(rec, count):
     row = (lo & np.uint64(0xFFFFFFFF)).astype(np.uint32).view(np.int32)
     power = (lo >> np.uint64(32)).astype(np.uint32).view(np.float32)
     return row.astype(np.int64), raw[:, 1].copy(), power.astype(np.float32)
+
+
+def fft_variants(n=0):
+    """Names of the compiled standalone FFT forms of length n (0 = all)."""
+    k = load().fdas_fft_variants(int(n), None, 0)
+    if k < 0:
+        _check(k, "fdas_fft_variants")
+    buf = C.create_string_buffer(64 * (k + 1))
+    load().fdas_fft_variants(int(n), buf, len(buf))
+    return [x for x in buf.value.decode().split("\n") if x]
+
+
+class FFT:
+    """Standalone batched complex FFT of length n (the correlation kernel's
+    shared-memory FFT on its own)."""
+
+    def __init__(self, n, elems_per_thread=0, device=None):
+        import torch
+        self._lib = load()
+        dev = torch.cuda.current_device() if device is None else int(device)
+        self.device = dev
+        h = C.c_void_p()
+        _check(self._lib.fdas_fft_plan(C.byref(h), int(n), int(elems_per_thread), dev,
+                                       _stream(dev)), "fdas_fft_plan")
+        self._h = h
+        i = FftInfoC()
+        _check(self._lib.fdas_fft_get_info(self._h, C.byref(i)), "fdas_fft_get_info")
+        self.n, self.elems_per_thread = i.n, i.elems_per_thread
+        self.threads, self.transforms_per_block = i.threads, i.transforms_per_block
+        self.kernel = i.kernel.decode()
+
+    def __call__(self, x, out=None, direction=-1):
+        """Transforms of the rows of a complex64 CUDA tensor [batch, n]
+        (unnormalised; direction -1 forward, +1 inverse)."""
+        import torch
+        if x.dtype != torch.complex64 or not x.is_cuda or x.dim() != 2 or x.shape[1] != self.n:
+            raise TypeError(f"need a complex64 CUDA tensor [batch, {self.n}]")
+        x = x.contiguous()
+        if out is None:
+            out = torch.empty_like(x)
+        _check(self._lib.fdas_fft_exec(self._h, C.c_void_p(x.data_ptr()),
+                                       C.c_void_p(out.data_ptr()), x.shape[0], int(direction),
+                                       _stream(x.device)), "fdas_fft_exec")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(self._lib.fdas_fft_destroy(self._h), "fdas_fft_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 def convolve(spectrum, zmax, dz, m=0, seg_len=0, precision="fp32", flags=0):

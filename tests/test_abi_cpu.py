@@ -131,3 +131,30 @@ def test_kernel_variant_listing():
         assert any("_split" in n for n in sub) and any("_split" not in n for n in sub)
     r = fdas.resolve(100, 2, 256, 0, "bf16", fdas.FLAG_SPLIT)
     assert (r.seg_len, r.flags) == (4096, fdas.FLAG_SPLIT)
+
+
+def test_fft_variant_listing():
+    names = fdas.fft_variants()
+    assert len(names) >= 8
+    assert [n for n in names if n.startswith("fft_L1024_")] == fdas.fft_variants(1024)
+    assert len(fdas.fft_variants(1024)) == 4
+    assert fdas.fft_variants(3) == []
+
+
+@pytest.mark.parametrize("n,elems,status", [(1000, 0, fdas.ERR_INVALID), (1, 0, fdas.ERR_INVALID),
+                                            (1024, 3, fdas.ERR_INVALID),
+                                            (1024, -2, fdas.ERR_INVALID),
+                                            (1 << 20, 0, fdas.ERR_UNSUPPORTED),
+                                            (1024, 32, fdas.ERR_UNSUPPORTED)])
+def test_fft_plan_rejects_on_host(lib, n, elems, status):
+    h = C.c_void_p(1234)
+    assert lib.fdas_fft_plan(C.byref(h), n, elems, 0, None) == status
+    assert not h.value  # cleared on failure
+    assert lib.fdas_fft_plan(None, 1024, 0, 0, None) == fdas.ERR_INVALID
+    assert lib.fdas_fft_plan(C.byref(h), 1024, 0, -1, None) == fdas.ERR_INVALID
+
+
+def test_fft_exec_and_destroy_reject_null_plan(lib):
+    assert lib.fdas_fft_exec(None, None, None, 1, -1, None) == fdas.ERR_INVALID
+    assert lib.fdas_fft_destroy(None) == fdas.OK
+    assert lib.fdas_fft_get_info(None, None) == fdas.ERR_INVALID
