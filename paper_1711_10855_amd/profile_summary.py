@@ -24,8 +24,8 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-KERNEL_SOURCES = ["csrc/ols_fp32.hip", "csrc/fft_radix.hpp", "csrc/ols_mixed.hip",
-                  "csrc/batch.hip"]
+KERNEL_SOURCES = ["csrc/ols_fp32.hip", "csrc/fft_radix.hpp", "csrc/fft_block.hpp",
+                  "csrc/ols_mixed.hip", "csrc/ols_variants.hpp"]
 
 
 def source_hash() -> str:
