@@ -16,6 +16,8 @@ Acceleration of the GPU Fourier Domain Acceleration Search Algorithm"):
   (Section 2) with naive DFT matrices built from eq. 3.
 * ``fft``        -- the unnormalised DFT of eq. 3 in both directions, for the
   standalone batched FFT.
+* ``frontend``   -- real series -> spectrum: real DFT, Nyquist dropped, DC
+  zeroed, median normalisation to unit mean noise power.
 """
 
 from .templates import (  # noqa: F401
@@ -37,3 +39,4 @@ from .correlate import (  # noqa: F401
     candidates_direct,
 )
 from .fft import dft_naive, dft64  # noqa: F401
+from .frontend import rfft_naive, spectrum64  # noqa: F401
