@@ -245,6 +245,30 @@ int fdas_fft_destroy(fdas_fft_t plan);
  * fdas_kernel_variants.                                                      */
 int fdas_fft_variants(int n, char *buf, size_t len);
 
+/* ---- device front end --------------------------------------------------
+ * The spectrum the correlation runs on (Section 1), made on the device from
+ * a real series x[0 .. n): A[k] = sum_j x[j] exp(-2 pi i j k / n) (eq. 3
+ * sign) for k in [0, n/2) (the Nyquist bin is dropped), A[0] = 0, then
+ * A *= sqrt(ln 2 / median_{k=1..n/2-1} |A[k]|^2), which gives white noise unit
+ * mean power (no scaling when that median is 0; for an even count the median
+ * is the mean of the two middle values). FP32 throughout.               */
+typedef struct fdas_frontend_s *fdas_frontend_t;
+
+/* n: a power of two in [128, 2^25]. Allocates the plan's scratch on `device`
+ * (12 n / 2 bytes plus twiddle tables); synchronises `stream`.              */
+int fdas_frontend_plan(fdas_frontend_t *out, int64_t n, int device, void *stream);
+/* series   : device float [n], 8-byte aligned.
+ * spectrum : device complex64 [n/2], 8-byte aligned; may be the series' own
+ *            buffer (the series is consumed before the first write); any
+ *            other overlap is rejected.
+ * stats    : NULL, or device float [2] receiving (scale, median |A|^2).
+ * Asynchronous on `stream`; kernels only, no allocation. A plan may be used
+ * from one stream at a time (it owns the scratch).                          */
+int fdas_frontend_exec(fdas_frontend_t plan, const float *series, void *spectrum, float *stats,
+                       void *stream);
+/* NULL is allowed. Synchronises the plan's device.                          */
+int fdas_frontend_destroy(fdas_frontend_t plan);
+
 /* Static description of a status code.                                      */
 const char *fdas_status_string(int status);
 

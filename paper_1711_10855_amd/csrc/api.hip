@@ -13,6 +13,7 @@
 
 #include "fdas.h"
 #include "fft_batch.hpp"
+#include "frontend.hpp"
 #include "ols_variants.hpp"
 #include "plan.hpp"
 
@@ -123,6 +124,16 @@ struct fdas_fft_s {
   int device;
   const fdas::FftVariant *v;
   fdas::c32 *tw;
+};
+
+// Device front end: geometry, twiddle tables and scratch.
+struct fdas_frontend_s {
+  int device;
+  int64_t n;
+  fdas::FrontendGeom g;
+  fdas::c32 *tw1, *tw2, *work;
+  float *pw;
+  void *sel;
 };
 
 namespace fdas {
@@ -365,6 +376,100 @@ int fdas_fft_destroy(fdas_fft_t plan) {
   delete plan;
   if (e == hipSuccess) e = f;
   return e == hipSuccess ? FDAS_OK : hip_error(e, "fdas_fft_destroy");
+}
+
+static void free_frontend(fdas_frontend_t p) {
+  if (!p) return;
+  if (p->tw1) (void)hipFree(p->tw1);
+  if (p->tw2) (void)hipFree(p->tw2);
+  if (p->work) (void)hipFree(p->work);
+  if (p->pw) (void)hipFree(p->pw);
+  if (p->sel) (void)hipFree(p->sel);
+  delete p;
+}
+
+int fdas_frontend_plan(fdas_frontend_t *out, int64_t n, int device, void *stream) {
+  if (!out) return set_error(FDAS_ERR_INVALID, "null plan pointer");
+  *out = nullptr;
+  if (n < 128 || n > ((int64_t)1 << 25) || (n & (n - 1)))
+    return set_error(FDAS_ERR_INVALID, "series length %lld is not a power of two in [128, 2^25]",
+                     (long long)n);
+  if (device < 0) return set_error(FDAS_ERR_INVALID, "device %d < 0", device);
+  const int64_t M = n / 2;
+  int lg = 0;
+  while (((int64_t)1 << lg) < M) ++lg;
+  FrontendGeom g{};
+  g.M = M;
+  if (M <= 4096) {
+    g.N1 = (int)M;
+    g.N2 = 1;
+  } else {
+    g.N1 = 1 << ((lg + 1) / 2);
+    g.N2 = 1 << (lg / 2);
+  }
+  int st = find_fft(g.N1, 0, &g.f1);
+  if (st == FDAS_OK && g.N2 > 1) st = find_fft(g.N2, 0, &g.f2);
+  if (st != FDAS_OK) return st;
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess) return hip_error(e, "hipGetDeviceCount");
+  if (device >= ndev) return set_error(FDAS_ERR_INVALID, "device %d of %d", device, ndev);
+  DeviceGuard guard(device);
+  if (guard.err != hipSuccess) return hip_error(guard.err, "hipSetDevice");
+  auto *p = new (std::nothrow) fdas_frontend_s{};
+  if (!p) return set_error(FDAS_ERR_NOMEM, "host allocation");
+  p->device = device;
+  p->n = n;
+  e = hipMalloc(&p->tw1, (size_t)g.N1 * sizeof(c32));
+  if (e == hipSuccess && g.N2 > 1) e = hipMalloc(&p->tw2, (size_t)g.N2 * sizeof(c32));
+  if (e == hipSuccess) e = hipMalloc(&p->work, (size_t)M * sizeof(c32));
+  if (e == hipSuccess) e = hipMalloc(&p->pw, (size_t)M * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&p->sel, frontend_sel_bytes());
+  if (e != hipSuccess) {
+    free_frontend(p);
+    return set_error(FDAS_ERR_NOMEM, "front-end buffers: %s", hipGetErrorString(e));
+  }
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  e = launch_twiddles(p->tw1, g.N1, s);
+  if (e == hipSuccess && g.N2 > 1) e = launch_twiddles(p->tw2, g.N2, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    free_frontend(p);
+    return hip_error(e, "front-end twiddles");
+  }
+  g.tw1 = p->tw1;
+  g.tw2 = p->tw2;
+  p->g = g;
+  *out = p;
+  return FDAS_OK;
+}
+
+int fdas_frontend_exec(fdas_frontend_t plan, const float *series, void *spectrum, float *stats,
+                       void *stream) {
+  if (!plan) return set_error(FDAS_ERR_INVALID, "null plan");
+  if (!series || !spectrum) return set_error(FDAS_ERR_INVALID, "null sample buffer");
+  if (reinterpret_cast<uintptr_t>(series) % 8 || reinterpret_cast<uintptr_t>(spectrum) % 8 ||
+      reinterpret_cast<uintptr_t>(stats) % 4)
+    return set_error(FDAS_ERR_INVALID, "series and spectrum must be 8-byte aligned");
+  const char *a = reinterpret_cast<const char *>(series);
+  const char *b = reinterpret_cast<const char *>(spectrum);
+  const int64_t nb = plan->n * 4;  // both buffers span 4 n bytes
+  if (a != b && a < b + nb && b < a + nb)
+    return set_error(FDAS_ERR_INVALID, "series and spectrum overlap without being equal");
+  DeviceGuard guard(plan->device);
+  if (guard.err != hipSuccess) return hip_error(guard.err, "hipSetDevice");
+  const hipError_t e = launch_frontend(plan->g, series, static_cast<c32 *>(spectrum), plan->work,
+                                       plan->pw, plan->sel, stats,
+                                       static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? FDAS_OK : hip_error(e, "front-end launch");
+}
+
+int fdas_frontend_destroy(fdas_frontend_t plan) {
+  if (!plan) return FDAS_OK;
+  DeviceGuard guard(plan->device);
+  const hipError_t e = hipDeviceSynchronize();
+  free_frontend(plan);
+  return e == hipSuccess ? FDAS_OK : hip_error(e, "fdas_frontend_destroy");
 }
 
 int fdas_fft_variants(int n, char *buf, size_t len) {

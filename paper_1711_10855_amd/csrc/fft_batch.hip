@@ -131,6 +131,8 @@ static constexpr FftVariant make_fft(const char *name) {
 // Name: fft_L<length>_e<elements per thread>_r<radices>[x<transforms per block>]
 // The first entry for a length is its default.
 static const FftVariant kFftVariants[] = {
+    make_fft<Geo<64, 4, 16, 4>, 32>("fft_L64_e16_r16.4x32"),
+    make_fft<Geo<128, 8, 8, 16>, 16>("fft_L128_e16_r8.16x16"),
     make_fft<Geo<256, 16, 16, 16>, 4>("fft_L256_e16_r16.16x4"),
     make_fft<Geo<512, 32, 2, 16, 16>, 4>("fft_L512_e16_r2.16.16x4"),
     make_fft<Geo<1024, 64, 4, 16, 16>, 4>("fft_L1024_e16_r4.16.16x4"),

@@ -36,7 +36,8 @@ EXPORTS = (
     "fdas_plan_get_info", "fdas_plan_bank", "fdas_convolve", "fdas_convolve_batch",
     "fdas_destroy", "fdas_status_string", "fdas_last_error", "fdas_kernel_variants",
     "fdas_convolve_candidates", "fdas_fft_plan", "fdas_fft_get_info", "fdas_fft_exec",
-    "fdas_fft_destroy", "fdas_fft_variants",
+    "fdas_fft_destroy", "fdas_fft_variants", "fdas_frontend_plan", "fdas_frontend_exec",
+    "fdas_frontend_destroy",
 )
 
 
@@ -121,6 +122,12 @@ def load():
     lib.fdas_fft_destroy.restype = C.c_int
     lib.fdas_fft_variants.argtypes = [C.c_int, C.c_char_p, C.c_size_t]
     lib.fdas_fft_variants.restype = C.c_int
+    lib.fdas_frontend_plan.argtypes = [P(C.c_void_p), C.c_int64, C.c_int, C.c_void_p]
+    lib.fdas_frontend_plan.restype = C.c_int
+    lib.fdas_frontend_exec.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.fdas_frontend_exec.restype = C.c_int
+    lib.fdas_frontend_destroy.argtypes = [C.c_void_p]
+    lib.fdas_frontend_destroy.restype = C.c_int
     lib.fdas_last_error.argtypes = []
     lib.fdas_last_error.restype = C.c_char_p
     _lib = lib
@@ -364,6 +371,53 @@ class FFT:
     def close(self):
         if getattr(self, "_h", None):
             _check(self._lib.fdas_fft_destroy(self._h), "fdas_fft_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class FrontEnd:
+    """Device front end: real series of n samples (a power of two) -> the
+    normalised complex spectrum of n/2 bins the correlation runs on."""
+
+    def __init__(self, n, device=None):
+        import torch
+        self._lib = load()
+        dev = torch.cuda.current_device() if device is None else int(device)
+        self.device, self.n = dev, int(n)
+        h = C.c_void_p()
+        _check(self._lib.fdas_frontend_plan(C.byref(h), self.n, dev, _stream(dev)),
+               "fdas_frontend_plan")
+        self._h = h
+
+    def __call__(self, series, out=None, stats=None):
+        """complex64 spectrum [n/2] of a float32 CUDA series [n]; `stats`, a
+        float32 CUDA tensor [2], receives (scale, median |A|^2)."""
+        import torch
+        if series.dtype != torch.float32 or not series.is_cuda or series.shape != (self.n,):
+            raise TypeError(f"need a float32 CUDA tensor [{self.n}]")
+        series = series.contiguous()
+        if out is None:
+            out = torch.empty(self.n // 2, dtype=torch.complex64, device=series.device)
+        st = C.c_void_p(stats.data_ptr()) if stats is not None else None
+        _check(self._lib.fdas_frontend_exec(self._h, C.c_void_p(series.data_ptr()),
+                                            C.c_void_p(out.data_ptr()), st,
+                                            _stream(series.device)), "fdas_frontend_exec")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(self._lib.fdas_frontend_destroy(self._h), "fdas_frontend_destroy")
             self._h = None
 
     def __del__(self):

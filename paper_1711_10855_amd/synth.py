@@ -142,8 +142,8 @@ def _draw_chirps(rng, count, nbins, m, zlim, snr_lo, snr_hi):
     return out
 
 
-def single_series(name: str):
-    """Spectrum (complex64) and injected chirps for a single-series workload."""
+def single_series_samples(name: str):
+    """Time series (float64) and injected chirps of a single-series workload."""
     w = WORKLOADS[name]
     if w.nseries != 1:
         raise ValueError(f"{name} is a batched workload")
@@ -152,7 +152,12 @@ def single_series(name: str):
         chirps = [Chirp(5000.3, 7.0, 20.0, float(rng.uniform(0.0, 2.0 * math.pi)))]
     else:
         chirps = _draw_chirps(rng, 8, w.nbins, w.m, 90.0, 8.0, 30.0)
-    x = make_series(w.n_samples, chirps, rng)
+    return make_series(w.n_samples, chirps, rng), chirps
+
+
+def single_series(name: str):
+    """Spectrum (complex64) and injected chirps for a single-series workload."""
+    x, chirps = single_series_samples(name)
     a = make_spectrum(x).astype(np.complex64)
     return a, chirps
 

@@ -121,7 +121,7 @@ def test_null_and_bad_arguments(lib):
 
 def test_kernel_variant_listing():
     names = fdas.kernel_variants()
-    assert len(names) >= 8
+    assert len(names) >= 10
     for L in (256, 512, 1024, 2048, 4096, 8192, 16384):
         sub = fdas.kernel_variants(L, "fp32")
         assert sub and all(f"_L{L}_" in n for n in sub)
@@ -135,7 +135,7 @@ def test_kernel_variant_listing():
 
 def test_fft_variant_listing():
     names = fdas.fft_variants()
-    assert len(names) >= 8
+    assert len(names) >= 10
     assert [n for n in names if n.startswith("fft_L1024_")] == fdas.fft_variants(1024)
     assert len(fdas.fft_variants(1024)) == 4
     assert fdas.fft_variants(3) == []
@@ -158,3 +158,17 @@ def test_fft_exec_and_destroy_reject_null_plan(lib):
     assert lib.fdas_fft_exec(None, None, None, 1, -1, None) == fdas.ERR_INVALID
     assert lib.fdas_fft_destroy(None) == fdas.OK
     assert lib.fdas_fft_get_info(None, None) == fdas.ERR_INVALID
+
+
+@pytest.mark.parametrize("n", [0, 64, 100, 1000, 1 << 26, -128])
+def test_frontend_plan_rejects_on_host(lib, n):
+    h = C.c_void_p(1234)
+    assert lib.fdas_frontend_plan(C.byref(h), n, 0, None) == fdas.ERR_INVALID
+    assert not h.value
+
+
+def test_frontend_exec_and_destroy_reject_null_plan(lib):
+    assert lib.fdas_frontend_plan(None, 1024, 0, None) == fdas.ERR_INVALID
+    assert lib.fdas_frontend_plan(C.byref(C.c_void_p()), 1024, -1, None) == fdas.ERR_INVALID
+    assert lib.fdas_frontend_exec(None, None, None, None, None) == fdas.ERR_INVALID
+    assert lib.fdas_frontend_destroy(None) == fdas.OK
