@@ -250,8 +250,8 @@ int fdas_fft_variants(int n, char *buf, size_t len);
  * a real series x[0 .. n): A[k] = sum_j x[j] exp(-2 pi i j k / n) (eq. 3
  * sign) for k in [0, n/2) (the Nyquist bin is dropped), A[0] = 0, then
  * A *= sqrt(ln 2 / median_{k=1..n/2-1} |A[k]|^2), which gives white noise unit
- * mean power (no scaling when that median is 0; for an even count the median
- * is the mean of the two middle values). FP32 throughout.               */
+ * mean power (no scaling when that median is 0; n/2 - 1 is odd, so the
+ * median is the middle value). FP32 throughout.                           */
 typedef struct fdas_frontend_s *fdas_frontend_t;
 
 /* n: a power of two in [128, 2^25]. Allocates the plan's scratch on `device`

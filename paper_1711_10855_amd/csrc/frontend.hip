@@ -12,8 +12,9 @@
 //      E = (Z[k] + conj Z[M-k]) / 2 and O = (Z[k] - conj Z[M-k]) / 2i,
 //      gives bins 0 .. M-1 of the real transform (eq. 3 sign; the Nyquist bin
 //      is not formed), and |A[k]|^2;
-//   3. the median of |A[k]|^2 over bins 1 .. M-1 by a three-pass radix select
-//      on the bit patterns (non-negative floats order as unsigned integers);
+//   3. the median of |A[k]|^2 over bins 1 .. M-1 (an odd count, M being a
+//      power of two) by a three-pass radix select on the bit patterns
+//      (non-negative floats order as unsigned integers);
 //   4. A[k] *= sqrt(ln 2 / median) (unit mean noise power; unscaled when the
 //      median is 0) and A[0] = 0.
 // Every step is a kernel on the caller's stream; nothing returns to the host.
@@ -32,11 +33,11 @@ namespace fdas {
 constexpr int kSelBins = 2048;  // widest radix-select digit (11 bits)
 
 struct SelState {
-  unsigned prefix[2];  // selected high bits of the two order statistics
-  unsigned mask;       // bits fixed so far
-  unsigned rank[2];    // remaining rank inside the current prefix
-  unsigned pad[3];
-  unsigned hist[2][kSelBins];
+  unsigned prefix;  // selected high bits of the order statistic
+  unsigned mask;    // bits fixed so far
+  unsigned rank;    // remaining rank inside the current prefix
+  unsigned pad;
+  unsigned hist[kSelBins];
 };
 
 // [rows][cols] -> [cols][rows], with out[c][r] = in[r][c] * W_M^(r c) when TW
@@ -95,71 +96,65 @@ __global__ void __launch_bounds__(256)
   P[k] = __builtin_fmaf(r.x, r.x, r.y * r.y);
 }
 
-__global__ void __launch_bounds__(256) sel_init_kernel(SelState *st, unsigned r0, unsigned r1) {
-  for (int i = threadIdx.x; i < 2 * kSelBins; i += blockDim.x) (&st->hist[0][0])[i] = 0u;
+__global__ void __launch_bounds__(256) sel_init_kernel(SelState *st, unsigned rank) {
+  for (int i = threadIdx.x; i < kSelBins; i += blockDim.x) st->hist[i] = 0u;
   if (threadIdx.x == 0) {
-    st->prefix[0] = st->prefix[1] = 0u;
+    st->prefix = 0u;
     st->mask = 0u;
-    st->rank[0] = r0;
-    st->rank[1] = r1;
+    st->rank = rank;
   }
 }
 
-// Histogram of the next digit of the elements that match each prefix.
+// Histogram of the next digit of the elements that match the prefix.
 __global__ void __launch_bounds__(256)
     sel_hist_kernel(const float *__restrict__ P_, int64_t count, SelState *__restrict__ st,
                     int shift, int nb) {
-  __shared__ unsigned h[2][kSelBins];
+  __shared__ unsigned h[kSelBins];
   const auto P = to_global(reinterpret_cast<const unsigned *>(P_));
-  for (int i = threadIdx.x; i < 2 * nb; i += blockDim.x) h[i / nb][i % nb] = 0u;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) h[i] = 0u;
   __syncthreads();
-  const unsigned mask = st->mask, p0 = st->prefix[0], p1 = st->prefix[1];
+  const unsigned mask = st->mask, prefix = st->prefix;
   const unsigned dm = (unsigned)nb - 1u;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
        i += (int64_t)gridDim.x * blockDim.x) {
     const unsigned u = P[i];
-    const unsigned d = (u >> shift) & dm;
-    if ((u & mask) == p0) atomicAdd(&h[0][d], 1u);
-    if ((u & mask) == p1) atomicAdd(&h[1][d], 1u);
+    if ((u & mask) == prefix) atomicAdd(&h[(u >> shift) & dm], 1u);
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < 2 * nb; i += blockDim.x) {
-    const unsigned v = h[i / nb][i % nb];
-    if (v) atomicAdd(&st->hist[i / nb][i % nb], v);
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+    const unsigned v = h[i];
+    if (v) atomicAdd(&st->hist[i], v);
   }
 }
 
-// Choose the digit that holds each rank; clear the histograms for the next
-// pass. One block of 256 threads, nb / 256 bins per thread.
+// Choose the digit that holds the rank; clear the histogram for the next
+// pass. One block of 256 threads; the histogram is staged in LDS so the
+// serial part of the scan touches LDS only.
 __global__ void __launch_bounds__(256) sel_pick_kernel(SelState *st, int shift, int nb) {
-  __shared__ unsigned part[2][256];
-  __shared__ unsigned pick[2][2];  // digit, count below it
+  __shared__ unsigned hh[kSelBins];
+  __shared__ unsigned part[256];
   const int per = nb / 256;
   const int t = threadIdx.x;
-  for (int s = 0; s < 2; ++s) {
-    unsigned sum = 0u;
-    for (int j = 0; j < per; ++j) sum += st->hist[s][t * per + j];
-    part[s][t] = sum;
+  unsigned sum = 0u;
+  for (int j = 0; j < per; ++j) {
+    const unsigned v = st->hist[t * per + j];
+    hh[t * per + j] = v;
+    sum += v;
   }
+  part[t] = sum;
   __syncthreads();
-  if (t < 2) {
-    const int s = t;
-    const unsigned rank = st->rank[s];
+  for (int j = 0; j < per; ++j) st->hist[t * per + j] = 0u;
+  if (t == 0) {
+    const unsigned rank = st->rank;
     unsigned below = 0u;
     int chunk = 0;
-    while (chunk < 255 && below + part[s][chunk] <= rank) below += part[s][chunk++];
+    while (chunk < 255 && below + part[chunk] <= rank) below += part[chunk++];
     int d = chunk * per;
-    while (d < chunk * per + per - 1 && below + st->hist[s][d] <= rank) below += st->hist[s][d++];
-    pick[s][0] = (unsigned)d;
-    pick[s][1] = below;
+    while (d < chunk * per + per - 1 && below + hh[d] <= rank) below += hh[d++];
+    st->prefix |= (unsigned)d << shift;
+    st->rank = rank - below;
+    st->mask |= ((unsigned)nb - 1u) << shift;
   }
-  __syncthreads();
-  for (int i = t; i < 2 * nb; i += blockDim.x) st->hist[i / nb][i % nb] = 0u;
-  if (t < 2) {
-    st->prefix[t] |= pick[t][0] << shift;
-    st->rank[t] -= pick[t][1];
-  }
-  if (t == 0) st->mask |= ((unsigned)nb - 1u) << shift;
 }
 
 // A[k] *= sqrt(ln 2 / median), A[0] = 0; stats = (scale, median) if given.
@@ -167,8 +162,7 @@ __global__ void __launch_bounds__(256)
     normalise_kernel(c32 *__restrict__ A_, int64_t M, const SelState *__restrict__ st,
                      float *__restrict__ stats) {
   const auto A = to_global(A_);
-  const double med =
-      0.5 * ((double)__uint_as_float(st->prefix[0]) + (double)__uint_as_float(st->prefix[1]));
+  const double med = (double)__uint_as_float(st->prefix);
   const float s = med > 0.0 ? (float)sqrt(0.69314718055994530942 / med) : 1.0f;
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k == 0 && stats) {
@@ -215,11 +209,10 @@ hipError_t launch_frontend(const FrontendGeom &g, const float *series, c32 *spec
   const unsigned blocks = (unsigned)((M + 255) / 256);
   hipLaunchKernelGGL(r2c_split_kernel, dim3(blocks), dim3(256), 0, s, work, spectrum, pw, M,
                      1.0f / (float)M);
-  // median of bins 1 .. M-1 (numpy's convention: mean of the two middle
-  // values for an even count)
+  // median of bins 1 .. M-1: M is a power of two, so the count is odd and the
+  // median is the single middle order statistic
   const int64_t cnt = M - 1;
-  const unsigned r0 = (unsigned)((cnt - 1) / 2), r1 = (unsigned)(cnt / 2);
-  hipLaunchKernelGGL(sel_init_kernel, dim3(1), dim3(256), 0, s, sel, r0, r1);
+  hipLaunchKernelGGL(sel_init_kernel, dim3(1), dim3(256), 0, s, sel, (unsigned)(cnt / 2));
   const int shifts[3] = {21, 10, 0}, widths[3] = {2048, 2048, 1024};
   const unsigned hblocks = (unsigned)std::min<int64_t>(1024, (cnt + 255) / 256);
   for (int pass = 0; pass < 3; ++pass) {
