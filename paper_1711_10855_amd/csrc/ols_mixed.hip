@@ -375,6 +375,13 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
   // 260 c + 16 n1 + 4 g (conflict-free 16-byte writes), and after the next
   // barrier wave w stores outputs [256 TPW w, 256 TPW (w + 1)) of the
   // segment, 1 KB contiguous per store instruction.
+  // A unit whose groups of 4 outputs lie wholly inside or wholly outside
+  // [half, half + U), below nbins and 16-byte aligned in every row stores one
+  // group per lane under a single predicate; others (the ragged last segment,
+  // rows not 16-byte aligned, odd m / 2) store element by element.
+  const bool vec_ok = half % 4 == 0 && ((int64_t)s * U - half) % 4 == 0 &&
+                      (int64_t)(s + 1) * U <= nbins && ld % 4 == 0 &&
+                      (reinterpret_cast<uintptr_t>(power_) & 15) == 0;
   auto store_staged = [&](int izr) {
     if (!CAND && !active) return;
     const auto prow = power + (int64_t)(izr - row_base) * ld;
@@ -393,10 +400,11 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
         }
         continue;
       }
-      if (o0 >= half && o0 + 3 < half + U && r0 + 3 < nbins &&
-          ((reinterpret_cast<uintptr_t>(prow + r0) & 15) == 0)) {
-        if constexpr (NT) __builtin_nontemporal_store(v, reinterpret_cast<gptr<f4>>(prow + r0));
-        else *reinterpret_cast<gptr<f4>>(prow + r0) = v;
+      if (vec_ok) {
+        if (o0 >= half && o0 < half + U) {
+          if constexpr (NT) __builtin_nontemporal_store(v, reinterpret_cast<gptr<f4>>(prow + r0));
+          else *reinterpret_cast<gptr<f4>>(prow + r0) = v;
+        }
       } else {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
