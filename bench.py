@@ -85,8 +85,13 @@ def traffic_from_profiles(kernel: str, workload: str):
     return None
 
 
-def cpu_baseline(a, zmax, dz, m, nz, sample_bins: int):
-    """The FP64 oracle (unchanged) on the first `sample_bins` bins, all rows."""
+def cpu_baseline(a, zmax, dz, m, nz, sample_bins: int, checks=()):
+    """The FP64 oracle (unchanged) on the first `sample_bins` bins, all rows.
+
+    `checks`: (name, plane, first_row, row_step, bar) with `plane` the GPU
+    result's first `sample_bins` columns (rows first_row, first_row +
+    row_step, ... of the oracle's rows); each gets max |P - P_ref| / max P_ref
+    over the columns that do not depend on bins beyond the sample."""
     import numpy as np
 
     import oracle
@@ -95,9 +100,20 @@ def cpu_baseline(a, zmax, dz, m, nz, sample_bins: int):
     p = oracle.plane_direct(sample, zmax, dz, m)
     dt = time.perf_counter() - t0
     pts = p.shape[0] * p.shape[1]
-    return {"value": pts / dt, "unit": "points/s", "cores": 1, "kind": "oracle",
+    base = {"value": pts / dt, "unit": "points/s", "cores": 1, "kind": "oracle",
             "sample": f"{nz} rows x first {sample_bins} bins of the input spectrum "
                       f"({pts} points, {dt:.1f} s, single process NumPy FP64 direct sum)"}
+    errors = {}
+    ncol = sample_bins - m // 2
+    for name, plane, r0, step, bar in checks:
+        rows = plane.shape[0] // step
+        ref = p[r0:r0 + rows, :ncol]
+        got = plane[::step][:rows, :ncol].astype(np.float64)
+        err = float(np.max(np.abs(got - ref)) / np.max(ref))
+        errors[name] = {"max_abs_err_over_max_ref": err, "bar": bar, "pass": err <= bar,
+                        "points": int(ref.size),
+                        "sample": f"{rows} rows x first {ncol} bins, against the oracle above"}
+    return base, errors
 
 
 def _time(fn, steps, warmup, stream):
@@ -117,9 +133,11 @@ def _time(fn, steps, warmup, stream):
     return start.elapsed_time(stop) / steps, wall
 
 
-def run_single(a_dev, zmax, dz, m, seg_len, prec, steps, warmup, flags=0, cand_thr=None):
+def run_single(a_dev, zmax, dz, m, seg_len, prec, steps, warmup, flags=0, cand_thr=None,
+               keep_cols=0):
     """Time fdas_convolve (or the candidate epilogue) on one resident
-    spectrum; returns a result dict."""
+    spectrum; returns a result dict (with the plane's first `keep_cols`
+    columns, copied to the host after the timing, as "check")."""
     import torch
 
     from paper_1711_10855_amd import fdas
@@ -131,21 +149,26 @@ def run_single(a_dev, zmax, dz, m, seg_len, prec, steps, warmup, flags=0, cand_t
     if cand_thr is None:
         out = torch.empty((nz, nbins), dtype=torch.float32, device=a_dev.device)
         ms, wall = _time(lambda: plan.convolve(a_dev, out=out), steps, warmup, stream)
+        check = out[:, :keep_cols].cpu().numpy() if keep_cols else None
         del out
     else:
         buf = plan.candidates(a_dev, cand_thr, capacity=1 << 20)
         ms, wall = _time(lambda: plan.candidates(a_dev, cand_thr, buf=buf), steps, warmup, stream)
         ncand = int(buf[1].cpu()[0])
+        check = None
     plan.close()
     points = nz * nbins
     bytes_launch = (4.0 * points if cand_thr is None else 16.0 * ncand) + 8.0 * nbins
     return {"points": points, "nz": nz, "nbins": nbins, "ms": ms, "wall": wall,
             "value": points / (ms * 1e-3), "bytes_launch": bytes_launch,
-            "achieved": bytes_launch / (ms * 1e-3) / 1e9, "info": info, "ncand": ncand}
+            "achieved": bytes_launch / (ms * 1e-3) / 1e9, "info": info, "ncand": ncand,
+            "check": check}
 
 
-def run_batch(name, prec, seg_len, nseries, steps, warmup, wave_bytes, flags=0):
-    """Time fdas_convolve_batch over a batched workload, in waves that fit."""
+def run_batch(name, prec, seg_len, nseries, steps, warmup, wave_bytes, flags=0, keep_cols=0):
+    """Time fdas_convolve_batch over a batched workload, in waves that fit;
+    afterwards the wave holding the longest series runs once more and that
+    series' first `keep_cols` plane columns come back as "check"."""
     import numpy as np
     import torch
 
@@ -191,15 +214,24 @@ def run_batch(name, prec, seg_len, nseries, steps, warmup, wave_bytes, flags=0):
 
     stream = torch.cuda.current_stream(dev)
     ms, wall = _time(step, steps, warmup, stream)
+    i0 = int(np.argmax([sp.nbins for sp in specs]))
+    check = None
+    if keep_cols:
+        for k, wv in enumerate(waves):
+            if i0 in wv:
+                sp, zm, outs = calls[k]
+                plan.convolve_batch(sp, zm, outs)
+                check = outs[wv.index(i0)][:, :keep_cols].cpu().numpy()
     plan.close()
     points = int(sum(r * sp.nbins for r, sp in zip(rows, specs)))
     nbins_total = int(sum(sp.nbins for sp in specs))
     bytes_launch = 4.0 * points + 8.0 * nbins_total
-    a0 = spectra[int(np.argmax([sp.nbins for sp in specs]))]
+    a0 = spectra[i0]
     return {"points": points, "nseries": len(specs), "waves": len(waves), "ms": ms,
             "wall": wall, "value": points / (ms * 1e-3), "bytes_launch": bytes_launch,
             "achieved": bytes_launch / (ms * 1e-3) / 1e9, "info": info, "gen_s": gen_s,
-            "sample_spectrum": a0, "zmax": w.zmax, "dz": w.dz, "m": w.m}
+            "sample_spectrum": a0, "zmax": w.zmax, "dz": w.dz, "m": w.m, "check": check,
+            "check_first_row": int(round((w.zmax - specs[i0].zmax) / w.dz))}
 
 
 def main():
@@ -236,28 +268,38 @@ def main():
         sys.exit(2)
     flags = (fdas.FLAG_SPLIT if args.split else 0) | (fdas.FLAG_INTERBIN if args.interbin else 0)
     compare = None
+    keep = 0 if args.no_cpu_baseline else args.cpu_sample_bins
+    bar = 1e-4 if prec == "fp32" else 1e-3
     if w.nseries == 1:
         seg_len = args.seg_len or (4096 if prec != "fp32" else w.seg_len)
         src = "fp32-paper" if args.workload == "mixed-paper" else args.workload
         a, _ = synth.single_series(src)
         a_dev = torch.from_numpy(a).to("cuda:0")
         r = run_single(a_dev, w.zmax, w.dz, w.m, seg_len, prec, args.steps, args.warmup, flags,
-                       args.candidates)
+                       args.candidates, keep_cols=min(keep, a.size))
+        step = 2 if args.interbin else 1  # integer-bin rows only
+        checks = [] if r["check"] is None else [(prec, r["check"], 0, step, bar)]
         if not args.no_compare and prec == "fp32" and not args.variant and w.m < 4096:
             c = run_single(a_dev, w.zmax, w.dz, w.m, 4096, "fp16", args.steps, args.warmup,
-                           flags & fdas.FLAG_INTERBIN, args.candidates)
+                           flags & fdas.FLAG_INTERBIN, args.candidates,
+                           keep_cols=min(keep, a.size))
             compare = {"fp16_mfma": {
                 "value": c["value"], "ms_per_step": c["ms"], "seg_len": 4096,
                 "kernel": c["info"].kernel, "frac": c["achieved"] / HBM_PEAK_GBS,
                 "speedup_vs_fp32": c["value"] / r["value"],
-                "error_bar": "max|P-P_ref| <= 1e-3 max P_ref (tested)"}}
-        cpu_in = (a, w.zmax, w.dz, w.m, r["nz"])
+                "error_bar": "max|P-P_ref| <= 1e-3 max P_ref"}}
+            if c["check"] is not None:
+                checks.append(("fp16_mfma", c["check"], 0, step, 1e-3))
+        cpu_in = (a, w.zmax, w.dz, w.m, r["nz"] // step)
         cfg = {"workload": args.workload, "nbins": r["nbins"], "nz": r["nz"]}
     else:
         seg_len = args.seg_len or (4096 if prec != "fp32" else w.seg_len)
         r = run_batch(args.workload, prec, seg_len, args.nseries, args.steps, args.warmup,
-                      int(args.wave_gb * 1e9), flags)
-        cpu_in = (r["sample_spectrum"], r["zmax"], r["dz"], r["m"], r["info"].nz)
+                      int(args.wave_gb * 1e9), flags, keep_cols=keep)
+        step = 2 if args.interbin else 1
+        checks = [] if r["check"] is None else [
+            (f"{prec} (longest series)", r["check"], r["check_first_row"], step, bar)]
+        cpu_in = (r["sample_spectrum"], r["zmax"], r["dz"], r["m"], r["info"].nz // step)
         cfg = {"workload": args.workload, "nseries": r["nseries"], "waves": r["waves"],
                "input_gen_s": round(r["gen_s"], 1)}
     info = r["info"]
@@ -298,8 +340,11 @@ def main():
         line["compare"] = compare
     if not args.no_cpu_baseline:
         a0, zmax, dz, m, nz = cpu_in
-        line["cpu_baseline"] = cpu_baseline(a0, zmax, dz, m, nz,
-                                            min(args.cpu_sample_bins, a0.size))
+        base, errors = cpu_baseline(a0, zmax, dz, m, nz, min(args.cpu_sample_bins, a0.size),
+                                    checks)
+        line["cpu_baseline"] = base
+        if errors:
+            line["error_vs_oracle"] = errors
     print(json.dumps(line))
 
 
