@@ -242,7 +242,8 @@ int fdas_fft_exec(fdas_fft_t plan, const void *in, void *out, int64_t batch, int
 /* NULL is allowed. Synchronises the plan's device.                          */
 int fdas_fft_destroy(fdas_fft_t plan);
 /* Names of the compiled FFT forms of length n (0 = all), as for
- * fdas_kernel_variants.                                                      */
+ * fdas_kernel_variants. The FDAS_FFT_VARIANT environment variable forces a
+ * form (by name) for new plans of its length.                               */
 int fdas_fft_variants(int n, char *buf, size_t len);
 
 /* ---- device front end --------------------------------------------------

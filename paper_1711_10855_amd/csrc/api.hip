@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -139,9 +140,18 @@ struct fdas_frontend_s {
 namespace fdas {
 
 // Compiled form for (n, elements per thread); elems 0 picks the default.
+// FDAS_FFT_VARIANT names a form that replaces the choice for its length.
 static int find_fft(int n, int elems, const FftVariant **out) {
   int count = 0;
   const FftVariant *vs = fft_variants(&count);
+  if (const char *force = std::getenv("FDAS_FFT_VARIANT")) {
+    for (int i = 0; i < count; ++i)
+      if (vs[i].L == n && std::strcmp(vs[i].name, force) == 0 &&
+          (elems == 0 || vs[i].E == elems)) {
+        *out = &vs[i];
+        return FDAS_OK;
+      }
+  }
   bool length_known = false;
   for (int i = 0; i < count; ++i) {
     if (vs[i].L != n) continue;

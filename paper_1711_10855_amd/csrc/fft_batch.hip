@@ -129,17 +129,24 @@ static constexpr FftVariant make_fft(const char *name) {
 }
 
 // Name: fft_L<length>_e<elements per thread>_r<radices>[x<transforms per block>]
+//       [_1b: one LDS buffer]
 // The first entry for a length is its default.
 static const FftVariant kFftVariants[] = {
     make_fft<Geo<64, 4, 16, 4>, 32>("fft_L64_e16_r16.4x32"),
     make_fft<Geo<128, 8, 8, 16>, 16>("fft_L128_e16_r8.16x16"),
     make_fft<Geo<256, 16, 16, 16>, 4>("fft_L256_e16_r16.16x4"),
+    make_fft<Geo<512, 32, 16, 2, 16>, 4>("fft_L512_e16_r16.2.16x4"),
     make_fft<Geo<512, 32, 2, 16, 16>, 4>("fft_L512_e16_r2.16.16x4"),
+    make_fft<Geo<1024, 64, 16, 4, 16>, 2>("fft_L1024_e16_r16.4.16x2"),
     make_fft<Geo<1024, 64, 4, 16, 16>, 4>("fft_L1024_e16_r4.16.16x4"),
+    make_fft<Geo<1024, 64, 16, 8, 8>, 2>("fft_L1024_e16_r16.8.8x2"),
     make_fft<Geo<1024, 512, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2>, 1>("fft_L1024_e2_r2^10"),
     make_fft<Geo<1024, 256, 4, 4, 4, 4, 4>, 1>("fft_L1024_e4_r4^5"),
     make_fft<Geo<1024, 128, 2, 8, 8, 8>, 2>("fft_L1024_e8_r2.8.8.8x2"),
+    make_fft<OneBuf<Geo<2048, 128, 16, 8, 16>>, 1>("fft_L2048_e16_r16.8.16x1_1b"),
+    make_fft<OneBuf<Geo<2048, 128, 16, 8, 16>>, 2>("fft_L2048_e16_r16.8.16x2_1b"),
     make_fft<Geo<2048, 128, 8, 16, 16>, 2>("fft_L2048_e16_r8.16.16x2"),
+    make_fft<OneBuf<Geo<4096, 256, 16, 16, 16>>, 1>("fft_L4096_e16_r16.16.16_1b"),
     make_fft<Geo<4096, 256, 16, 16, 16>, 1>("fft_L4096_e16_r16.16.16"),
 };
 

@@ -76,6 +76,13 @@ struct Geo {
   static constexpr int NBUF = (any_block() && 2 * LP * 8 <= 80 * 1024) ? 2 : 1;
 };
 
+// The same geometry with one LDS buffer (every block-wide exchange then
+// ends with a second barrier): half the LDS, so more blocks per CU.
+template <class G>
+struct OneBuf : G {
+  static constexpr int NBUF = 1;
+};
+
 template <class Gm>
 __device__ __forceinline__ int pad(int a) {
   return a + (a >> Gm::PADSH);

@@ -38,12 +38,19 @@ def _err(got, ref):
     return float(np.max(np.abs(got.astype(np.complex128) - ref)) / np.max(np.abs(ref)))
 
 
+@pytest.fixture
+def fft_form(monkeypatch):
+    """Force a compiled FFT form (by name) for plans made inside the test."""
+    return lambda name: monkeypatch.setenv("FDAS_FFT_VARIANT", name)
+
+
 @pytest.mark.parametrize("n,e,name", _forms())
 @pytest.mark.parametrize("direction", [-1, 1])
-def test_every_form_matches_the_dft(gpu, n, e, name, direction):
+def test_every_form_matches_the_dft(gpu, fft_form, n, e, name, direction):
     import torch
     x = _rand(37, n, seed=n + e + direction)
     print(f"fft {name} direction {direction} batch 37", flush=True)
+    fft_form(name)
     with gpu.FFT(n, e) as f:
         assert f.kernel == name and f.elems_per_thread == e
         got = f(torch.from_numpy(x).cuda(), direction=direction).cpu().numpy()
