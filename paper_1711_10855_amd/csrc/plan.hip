@@ -85,7 +85,7 @@ static int build_plan_with(fdas_plan_t *out, const fdas_params &p, int nz, int d
 // (U = L - m >= L/2 unless the caller fixed L) and a few template-group sizes
 // on a synthetic spectrum, keep the fastest per plane point. Results are
 // cached in a text file (FDAS_TUNE_CACHE, one line per key) keyed by device
-// architecture, CU count, m, nz and precision.
+// architecture, CU count, m, nz, precision, split form and segment length.
 struct TuneChoice {
   const OlsVariant *var = nullptr;
   int L = 0, zpb = 0;
@@ -103,8 +103,8 @@ static std::string tune_key(const fdas_params &p, int nz, int device) {
   for (auto &ch : arch)
     if (ch == ' ' || ch == ':') ch = '_';
   char buf[256];
-  std::snprintf(buf, sizeof(buf), "%s cu%d m%d nz%d prec%d L%d", arch.c_str(), cus, p.m, nz,
-                p.precision, p.seg_len);
+  std::snprintf(buf, sizeof(buf), "%s cu%d m%d nz%d prec%d split%d L%d", arch.c_str(), cus, p.m,
+                nz, p.precision, (p.flags & FDAS_FLAG_SPLIT) ? 1 : 0, p.seg_len);
   return buf;
 }
 
@@ -118,7 +118,7 @@ static const OlsVariant *variant_by_name(const char *name) {
   return nullptr;
 }
 
-static bool tune_cache_lookup(const std::string &key, TuneChoice *c) {
+static bool tune_cache_lookup(const std::string &key, const fdas_params &p, TuneChoice *c) {
   const char *path = std::getenv("FDAS_TUNE_CACHE");
   if (!path || !*path) return false;
   FILE *f = std::fopen(path, "r");
@@ -134,7 +134,9 @@ static bool tune_cache_lookup(const std::string &key, TuneChoice *c) {
     double ns = 0;
     if (std::sscanf(ln.c_str() + bar + 3, "%127s %d %d %lf", name, &L, &zpb, &ns) == 4) {
       const OlsVariant *v = variant_by_name(name);
-      if (v && v->L == L) {
+      // a line only counts for the precision and split form it was timed for
+      if (v && v->L == L && v->precision == p.precision &&
+          v->split == ((p.flags & FDAS_FLAG_SPLIT) ? 1 : 0)) {
         c->var = v;
         c->L = L;
         c->zpb = zpb;
@@ -238,7 +240,7 @@ int build_plan(fdas_plan_t *out, const fdas_params &p, int nz, int device, hipSt
     fdas_params q = p;
     const std::string key = tune_key(p, nz, device);
     TuneChoice c;
-    if (!tune_cache_lookup(key, &c)) {
+    if (!tune_cache_lookup(key, p, &c)) {
       int st = autotune(p, nz, device, s, &c);
       if (st != FDAS_OK) return st;
       tune_cache_store(key, c);

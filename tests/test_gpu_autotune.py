@@ -30,3 +30,24 @@ def test_autotune_choice_is_cached_and_correct(gpu, tmp_path, monkeypatch):
         assert p2.info.kernel == info.kernel
         assert p2.info.templates_per_block == info.templates_per_block
     assert len(cache.read_text().splitlines()) == 1   # served from the cache
+
+
+def test_tune_cache_separates_split_forms(gpu, tmp_path, monkeypatch):
+    """A cached choice for the plain 16-bit form is not reused for the hi+lo
+    split form (and vice versa): each gets its own line and its own kind of
+    kernel."""
+    import torch
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("FDAS_TUNE_CACHE", str(cache))
+    monkeypatch.delenv("FDAS_VARIANT", raising=False)
+    a = synth.small_random_spectrum(20000, seed=22)
+    ref = oracle.plane_direct(a, 8.0, 2.0, 64)
+    kernels = []
+    for flags, tol in ((gpu.FLAG_AUTOTUNE, 1e-3), (gpu.FLAG_AUTOTUNE | gpu.FLAG_SPLIT, 1e-5)):
+        print(f"autotune fp16 flags={flags}", flush=True)
+        with gpu.Plan(8.0, 2.0, 64, 0, "fp16", flags=flags) as p:
+            kernels.append(p.info.kernel)
+            out = p.convolve(torch.from_numpy(a).cuda()).cpu().numpy()
+        assert np.max(np.abs(out - ref)) <= tol * ref.max()
+    assert "_split" not in kernels[0] and "_split" in kernels[1]
+    assert len(cache.read_text().splitlines()) == 2
