@@ -7,7 +7,7 @@ of the hot kernel, FETCH_SIZE and WRITE_SIZE scaled by what the same counters
 read for a plain device copy of known size).
 
 Usage:
-  python -m paper_1711_10855_amd.profile_summary --dir gpurun_out \
+  python -m paper_1711_10855_amd.profile_summary --dir <rocprofv3 output dir> \
       --workload fp32-paper --kernel-match ols_ --name <summary-name> \
       --command "<the rocprofv3 commands that produced the CSVs>"
 """
@@ -57,7 +57,7 @@ def _one(pattern):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--dir", default="gpurun_out")
+    ap.add_argument("--dir", required=True, help="directory holding the rocprofv3 CSV runs")
     ap.add_argument("--workload", required=True)
     ap.add_argument("--kernel-match", default="ols_")
     ap.add_argument("--name", required=True)
