@@ -173,6 +173,20 @@ def kernel_variants(seg_len=0, precision=-1):
     return [x for x in buf.value.decode().split("\n") if x]
 
 
+def _plane_ok(out, rows, nbins, ld, device):
+    """Raise unless `out` can hold rows x nbins float32 values at row stride ld
+    on `device` (the kernels write through the pointer; a short or mistyped
+    buffer must never reach them)."""
+    import torch
+    if (not isinstance(out, torch.Tensor) or out.dtype != torch.float32 or out.device != device
+            or out.dim() != 2 or out.shape[0] != rows or out.stride(1) != 1):
+        raise TypeError(f"output must be a float32 tensor [{rows}, >= {nbins}] with unit column "
+                        f"stride on {device}")
+    if ld < nbins or out.shape[1] < nbins or (rows > 1 and out.stride(0) != ld):
+        raise ValueError(f"output rows hold {out.shape[1]} values at stride {out.stride(0)}; "
+                         f"need >= {nbins} at stride ld = {ld}")
+
+
 def _stream(device=None):
     import torch
     return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
@@ -256,6 +270,7 @@ class Plan:
             out = torch.empty((self.info.nz, ld), dtype=torch.float32, device=spectrum.device)
         else:
             ld = out.stride(0) if ld is None else int(ld)
+            _plane_ok(out, self.info.nz, nbins, ld, spectrum.device)
         _check(self._lib.fdas_convolve(self._h, C.c_void_p(spectrum.data_ptr()), nbins,
                                        C.c_void_p(out.data_ptr()), ld, _stream(spectrum.device)),
                "fdas_convolve")
@@ -278,6 +293,10 @@ class Plan:
             cnt = torch.empty(1, dtype=torch.int64, device=spectrum.device)
         else:
             rec, cnt = buf
+            if (rec.dtype != torch.int64 or rec.dim() != 2 or rec.shape[1] != 2
+                    or not rec.is_contiguous() or rec.device != spectrum.device
+                    or cnt.dtype != torch.int64 or cnt.numel() < 1 or cnt.device != spectrum.device):
+                raise TypeError("buf must be (int64 [capacity, 2], int64 [1]) on the spectrum's device")
             capacity = rec.shape[0]
         _check(self._lib.fdas_convolve_candidates(
             self._h, C.c_void_p(spectrum.data_ptr()), spectrum.numel(), float(threshold),
@@ -287,9 +306,19 @@ class Plan:
 
     def convolve_batch(self, spectra, zmaxs, outs):
         """Batched form: one launch over every series (see fdas_convolve_batch)."""
+        import torch
         n = len(spectra)
+        if not (n == len(zmaxs) == len(outs)) or n < 1:
+            raise ValueError("need equally many (>= 1) spectra, zmaxs and outputs")
+        per = 2 if self.params.flags & FLAG_INTERBIN else 1
         arr = (Series * n)()
         for i, (s, z, o) in enumerate(zip(spectra, zmaxs, outs)):
+            if s.dtype != torch.complex64 or not s.is_cuda or s.dim() != 1 or not s.is_contiguous():
+                raise TypeError(f"spectrum {i} must be a contiguous 1-D complex64 CUDA tensor")
+            span = 2 * float(z) / self.params.dz
+            if 0 <= float(z) <= self.params.zmax and abs(span - round(span)) < 1e-6:
+                # (other zmax values are the library's to reject)
+                _plane_ok(o, per * (int(round(span)) + 1), s.numel(), o.stride(0), s.device)
             arr[i] = Series(C.c_void_p(s.data_ptr()), s.numel(), float(z),
                             C.c_void_p(o.data_ptr()), o.stride(0))
         dev = spectra[0].device
@@ -363,6 +392,9 @@ class FFT:
         x = x.contiguous()
         if out is None:
             out = torch.empty_like(x)
+        elif (out.dtype != torch.complex64 or out.shape != x.shape or not out.is_contiguous()
+              or out.device != x.device):
+            raise TypeError(f"out must be a contiguous complex64 tensor {tuple(x.shape)} on {x.device}")
         _check(self._lib.fdas_fft_exec(self._h, C.c_void_p(x.data_ptr()),
                                        C.c_void_p(out.data_ptr()), x.shape[0], int(direction),
                                        _stream(x.device)), "fdas_fft_exec")
@@ -409,6 +441,12 @@ class FrontEnd:
         series = series.contiguous()
         if out is None:
             out = torch.empty(self.n // 2, dtype=torch.complex64, device=series.device)
+        elif (out.dtype != torch.complex64 or out.numel() != self.n // 2
+              or not out.is_contiguous() or out.device != series.device):
+            raise TypeError(f"out must be a contiguous complex64 tensor of {self.n // 2} values")
+        if stats is not None and (stats.dtype != torch.float32 or stats.numel() < 2
+                                  or not stats.is_contiguous() or stats.device != series.device):
+            raise TypeError("stats must be a contiguous float32 tensor of 2 values")
         st = C.c_void_p(stats.data_ptr()) if stats is not None else None
         _check(self._lib.fdas_frontend_exec(self._h, C.c_void_p(series.data_ptr()),
                                             C.c_void_p(out.data_ptr()), st,

@@ -172,3 +172,20 @@ def test_frontend_exec_and_destroy_reject_null_plan(lib):
     assert lib.fdas_frontend_plan(C.byref(C.c_void_p()), 1024, -1, None) == fdas.ERR_INVALID
     assert lib.fdas_frontend_exec(None, None, None, None, None) == fdas.ERR_INVALID
     assert lib.fdas_frontend_destroy(None) == fdas.OK
+
+
+def test_binding_rejects_output_buffers_that_do_not_fit():
+    """The binding checks output tensors before their pointers reach a kernel
+    (shape, dtype, row stride); exercised on host tensors."""
+    import torch
+    dev = torch.device("cpu")
+    ok = torch.empty((5, 120), dtype=torch.float32)
+    fdas._plane_ok(ok, 5, 100, 120, dev)
+    fdas._plane_ok(ok[:, :100], 5, 100, 120, dev)          # a column slice keeps stride 120
+    for bad, ld in ((torch.empty((4, 120)), 120),              # too few rows
+                    (torch.empty((5, 90)), 90),                # rows too short
+                    (torch.empty((5, 120), dtype=torch.float64), 120),
+                    (torch.empty((120, 5)).t(), 120),          # column stride != 1
+                    (ok, 100)):                                 # stride differs from ld
+        with pytest.raises((TypeError, ValueError)):
+            fdas._plane_ok(bad, 5, 100, ld, dev)
