@@ -588,9 +588,9 @@ static OlsVariant make_mixed(const char *name, int precision) {
   v.precision = precision;
   v.split = SPLIT ? 1 : 0;
   // The forward FFT costs several templates' worth of time here; units of
-  // about 50 templates measured fastest (17 to 101 swept on the paper-scale
-  // plane).
-  v.zpb_target = 52;
+  // up to 72 templates with a shorter last group measured fastest (17 to 101
+  // swept on the paper-scale plane).
+  v.zpb_target = 72;
   v.lay.L = 4096;
   v.lay.T = 256;
   v.lay.E = 16;

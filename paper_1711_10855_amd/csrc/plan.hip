@@ -70,12 +70,20 @@ static const OlsVariant *find_variant(int L, int precision, int split, const cha
   return (want && *want) ? nullptr : first;
 }
 
-// Templates per work unit: split nz into near-equal groups of at most
-// `target` (32 unless the variant fixes its own).
+// Templates per work unit. Without a target (plans that choose per launch),
+// near-equal groups of about 32. With a target: units of `target` templates
+// in group order and the remainder last, and fewer rows than the target
+// split about 3 : 1; work units are dispatched in group order, so the short
+// ones start last and fill the end of the launch (on the 2^21-bin plane this
+// measured 3-6% faster than equal groups at 65, 101 and 201 rows).
 static int default_zpb(int nz, int target) {
-  if (target <= 0) target = 32;
-  const int groups = (nz + target - 1) / target;
-  return (nz + groups - 1) / groups;
+  if (target <= 0) {
+    const int groups = (nz + 31) / 32;
+    return (nz + groups - 1) / groups;
+  }
+  if (nz > target) return target;
+  if (nz > 40) return (3 * nz + 3) / 4;
+  return nz;
 }
 
 static int build_plan_with(fdas_plan_t *out, const fdas_params &p, int nz, int device,
