@@ -369,8 +369,13 @@ int fdas_fft_exec(fdas_fft_t plan, const void *in, void *out, int64_t batch, int
   if (reinterpret_cast<uintptr_t>(in) % 8 || reinterpret_cast<uintptr_t>(out) % 8)
     return set_error(FDAS_ERR_INVALID, "sample buffers must be 8-byte aligned");
   const int64_t blocks = (batch + plan->v->G - 1) / plan->v->G;
-  if (blocks > (int64_t)INT_MAX || batch > INT64_MAX / plan->v->L)
+  if (blocks > (int64_t)INT_MAX || batch > INT64_MAX / (8 * (int64_t)plan->v->L))
     return set_error(FDAS_ERR_INVALID, "batch %lld too large", (long long)batch);
+  const char *a = static_cast<const char *>(in);
+  const char *b = static_cast<const char *>(out);
+  const int64_t nb = batch * 8 * (int64_t)plan->v->L;
+  if (a != b && a < b + nb && b < a + nb)
+    return set_error(FDAS_ERR_INVALID, "input and output overlap without being equal");
   DeviceGuard guard(plan->device);
   if (guard.err != hipSuccess) return hip_error(guard.err, "hipSetDevice");
   const hipError_t e = plan->v->launch(in, out, batch, direction, plan->tw,

@@ -104,3 +104,16 @@ def test_large_batch_sampled(gpu):
             got = X[rows].cpu().numpy()
             ref = oracle.dft64(x[rows].cpu().numpy(), -1)
             assert _err(got, ref) <= TOL, e
+
+
+def test_partly_overlapping_buffers_are_rejected(gpu):
+    import torch
+    n = 256
+    buf = torch.zeros((5, n), dtype=torch.complex64, device="cuda")
+    with gpu.FFT(n) as f:
+        lib = gpu.load()
+        import ctypes as C
+        st = lib.fdas_fft_exec(f._h, C.c_void_p(buf.data_ptr()),
+                               C.c_void_p(buf[1:].data_ptr()), 4, -1, None)
+        assert st == gpu.ERR_INVALID
+        f(buf, out=buf)  # in place is fine
