@@ -70,6 +70,8 @@ static const OlsVariant *find_variant(int L, int precision, int split, const cha
   return (want && *want) ? nullptr : first;
 }
 
+constexpr int kFp32UnitTarget = 40;
+
 // Templates per work unit. Without a target (plans that choose per launch),
 // near-equal groups of about 32. With a target: units of `target` templates
 // in group order and the remainder last (a remainder under a third of the
@@ -413,6 +415,11 @@ static int launch_zpb(fdas_plan_t pl, int64_t nsb) {
       best_zpb = zpb;
     }
   }
+  // On grids of two or more full rounds, units of 40 templates with the
+  // remainder last beat equal groups (the short units fill the end of the
+  // launch; 2-3% on the 2^21-bin plane at 65 and 101 rows).
+  const int tz = default_zpb(pl->nz, kFp32UnitTarget);
+  if (nsb * ((pl->nz + tz - 1) / tz) >= 2 * (int64_t)pl->slots) best_zpb = tz;
   return best_zpb;
 }
 
