@@ -156,6 +156,7 @@ def run_single(a_dev, zmax, dz, m, seg_len, prec, steps, warmup, flags=0, cand_t
         ms, wall = _time(lambda: plan.candidates(a_dev, cand_thr, buf=buf), steps, warmup, stream)
         ncand = int(buf[1].cpu()[0])
         check = None
+    info = plan.get_info()  # templates per unit as the timed launches chose them
     plan.close()
     points = nz * nbins
     bytes_launch = (4.0 * points if cand_thr is None else 16.0 * ncand) + 8.0 * nbins

@@ -39,6 +39,7 @@ struct fdas_plan_s {
   int cus = 0;
   bool zpb_forced = false;  // FDAS_ZPB or the autotuner fixed it
   int slots = 0;            // concurrently resident blocks of the grid kernel
+  int last_zpb = 0;         // templates per unit of the last single-series launch
 };
 
 static constexpr size_t kMaxGraphs = 8;
@@ -347,7 +348,7 @@ void plan_info(fdas_plan_t pl, fdas_plan_info *info) {
   info->precision = pl->p.precision;
   info->flags = pl->p.flags;
   info->threads = pl->var->T;
-  info->templates_per_block = pl->zpb;
+  info->templates_per_block = pl->last_zpb > 0 ? pl->last_zpb : pl->zpb;
   info->segments_per_block = pl->var->G;
   info->bank_bytes = pl->bank_bytes;
   info->plan_ms = pl->plan_ms;
@@ -429,6 +430,7 @@ static int plan_launch(fdas_plan_t pl, const void *spec, int64_t nbins, float *p
   if (nseg > INT_MAX / 2) return set_error(FDAS_ERR_UNSUPPORTED, "nbins %lld too large", (long long)nbins);
   const int64_t nsb = (nseg + pl->var->G - 1) / pl->var->G;
   const int zpb = launch_zpb(pl, nsb);
+  pl->last_zpb = zpb;
   const int64_t nzg = (pl->nz + zpb - 1) / zpb;
   if (nsb * nzg > (int64_t)UINT_MAX)
     return set_error(FDAS_ERR_UNSUPPORTED, "grid of %lld blocks too large", (long long)(nsb * nzg));
