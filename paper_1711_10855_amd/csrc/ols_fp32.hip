@@ -396,8 +396,8 @@ static const OlsVariant kFp32Variants[] = {
     make_variant<Geo<2048, 128, 8, 16, 16>, 1, false, true, 2>("fp32_L2048_t128_r8.16.16_tg_o2"),
     make_variant<Geo<2048, 256, 4, 8, 8, 8>, 1, true, true, 3>("fp32_L2048_t256_r4.8.8.8"),
     make_variant<Geo<2048, 256, 4, 8, 8, 8>, 1, false, true, 3>("fp32_L2048_t256_r4.8.8.8_tg"),
-    make_variant<Geo<4096, 256, 16, 16, 16>, 1, true, true, 2>("fp32_L4096_t256_r16.16.16_o2"),
     make_variant<Geo<4096, 256, 16, 16, 16>, 1, true, false, 2>("fp32_L4096_t256_r16.16.16_np"),
+    make_variant<Geo<4096, 256, 16, 16, 16>, 1, true, true, 2>("fp32_L4096_t256_r16.16.16_o2"),
     make_variant<Geo<4096, 256, 16, 16, 16>, 1, false, true, 2>("fp32_L4096_t256_r16.16.16_tg_o2"),
     make_variant<Geo<4096, 512, 8, 8, 8, 8>, 1, false, true>("fp32_L4096_t512_r8.8.8.8_tg"),
     make_variant<Geo<4096, 512, 8, 8, 8, 8>, 1, true, true, 2>("fp32_L4096_t512_r8.8.8.8_o2"),
