@@ -18,6 +18,9 @@ Acceleration of the GPU Fourier Domain Acceleration Search Algorithm"):
   standalone batched FFT.
 * ``frontend``   -- real series -> spectrum: real DFT, Nyquist dropped, DC
   zeroed, median normalisation to unit mean noise power.
+* ``peaks``      -- the candidate search after the plane (Section 3 names
+  it): points at or above a threshold that are local maxima of their 3 x 3
+  (z, r) neighbourhood, ties going to the lowest (z, r).
 """
 
 from .templates import (  # noqa: F401
@@ -40,3 +43,4 @@ from .correlate import (  # noqa: F401
 )
 from .fft import dft_naive, dft64  # noqa: F401
 from .frontend import rfft_naive, spectrum64  # noqa: F401
+from .peaks import peak_mask, peaks_from_plane, peaks_direct  # noqa: F401
