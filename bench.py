@@ -1,30 +1,44 @@
 """Benchmark of the FDAS correlation step on one MI355X.
 
-A step is one call of the hot path (segment load, forward FFT, per-template
+A step is one pass of the hot path (segment load, forward FFT, per-template
 product + inverse FFT, overlap discard, |.|^2 store) over the whole input of
-the workload. The default workload is the paper-scale plain-FP32 one (2^21
-bins, z in [-100, 100] step 2 -> 101 templates of width 256, segment FFT
-2048) producing the 101 x 2^21 FP32 power plane (847 MB). Inputs are resident
-in device memory before the timed region; the plan (templates, bank) is
-built once outside it and its time is reported separately. The same run also
-times the FP16 matrix-core form on the same input ("compare").
+the workload, with the inputs resident in device memory before the timed
+region. Plans (templates, bank) are built outside it; their time is
+reported separately.
 
-Other workloads (--workload): fp32-small, mixed-paper, batch-fp32 (512 series
-of uneven length, per-series zmax, one graph-captured launch per wave),
-batch-mixed-wide (256 series, z in [-200, 200], m 512, run in waves that fit
-device memory).
+Default workload: batch-mixed-wide -- 256 series of 2^22 samples (2^21
+complex bins each, 0-3 injected accelerated sinusoids), z in [-200, 200]
+step 2 (201 templates of width 512), run in waves of series whose planes fit
+the device memory budget, one graph-captured launch per wave. Three forms
+run on the same resident inputs: the FP16 matrix-core form, the BF16 hi+lo
+split form and plain FP32. `value` is the fastest 16-bit form whose error
+stays within 1e-3 of the largest oracle power on every series; `compare`
+holds the others with their speed-up over plain FP32.
 
-Prints ONE JSON line. `value` is z-r plane points per second; `roofline`
-prices the dominant kernel's algorithmic bytes per launch (4 B per plane
-point written + 8 B per input bin read) against the 8 TB/s HBM peak, with
-the kernel time measured by HIP events on the stream the kernel runs on;
-`cpu_baseline` times the FP64 oracle on a bounded sample of the same input.
+Other workloads (--workload): fp32-small, fp32-paper (one 2^21-bin plane,
+101 templates), mixed-paper, batch-fp32 (512 series of uneven length,
+per-series zmax; the FP32 plan's segment length is autotuned).
+
+Errors (`error_vs_oracle`, per form): every series of a batch is checked at
+sampled plane points (around each injected signal, at both edges and
+uniformly at random) against the FP64 oracle's direct sum at the same
+points, max|P - P_ref| / max P_ref per series; the series the oracle timing
+runs on are also checked on every row of their first bins.
+
+`roofline` prices the value form's kernel: algorithmic bytes (4 B per
+plane point written + 8 B per input bin read) over the kernel time measured
+by HIP events on the stream the kernel runs on, against the 8 TB/s HBM
+peak. `cpu_baseline` times the FP64 oracle (unchanged) on a bounded sample
+of the same input, in a process pool over bin ranges of the sampled series.
+
+Prints ONE JSON line.
 """
 
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -34,22 +48,42 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+SPLIT = 1          # FDAS_FLAG_SPLIT
+AUTOTUNE = 2       # FDAS_FLAG_AUTOTUNE
+INTERBIN = 4       # FDAS_FLAG_INTERBIN
+
+# form name -> (precision, flags)
+FORMS = {
+    "fp32": ("fp32", 0),
+    "fp16": ("fp16", 0),
+    "bf16": ("bf16", 0),
+    "fp16-split": ("fp16", SPLIT),
+    "bf16-split": ("bf16", SPLIT),
+}
+DEFAULT_FORMS = {"batch": "fp16,bf16-split,fp32", "single": "fp32,fp16"}
 
 
-def parse():
+def bar_of(form: str) -> float:
+    return 1e-4 if form == "fp32" else 1e-3
+
+
+def parse(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=200,
-                    help="untimed steps first (the GPU clock needs tens of ms of load "
-                         "to reach its steady state)")
-    ap.add_argument("--workload", default="fp32-paper")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup-s", type=float, default=0.5,
+                    help="after the warm-up steps, keep stepping until this many seconds of "
+                         "load have passed (the GPU clock needs tens of ms to settle)")
+    ap.add_argument("--workload", default="batch-mixed-wide")
+    ap.add_argument("--forms", default=None,
+                    help="comma-separated forms to time on the same inputs "
+                         f"(of {', '.join(FORMS)}); default batched: {DEFAULT_FORMS['batch']}, "
+                         f"single series: {DEFAULT_FORMS['single']}")
     ap.add_argument("--variant", default=None, help="force a compiled kernel variant")
     ap.add_argument("--zpb", type=int, default=None, help="templates per work unit")
-    ap.add_argument("--precision", default=None, help="override the workload precision")
-    ap.add_argument("--seg-len", type=int, default=None)
-    ap.add_argument("--split", action="store_true",
-                    help="mixed precisions: hi + lo split products (FDAS_FLAG_SPLIT)")
+    ap.add_argument("--seg-len", type=int, default=None,
+                    help="FP32 segment length (default: the workload's; batch-fp32 autotunes)")
     ap.add_argument("--interbin", action="store_true",
                     help="also the half-bin rows (FDAS_FLAG_INTERBIN): 2 nz rows per plane")
     ap.add_argument("--candidates", type=float, default=None, metavar="THR",
@@ -58,86 +92,268 @@ def parse():
     ap.add_argument("--nseries", type=int, default=None, help="batched: first N series only")
     ap.add_argument("--wave-gb", type=float, default=100.0,
                     help="batched: device memory budget for the planes of one wave")
-    ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--sample-points", type=int, default=2048,
+                    help="batched: random plane points per series checked against the oracle")
+    ap.add_argument("--no-check", action="store_true", help="skip the checks against the oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-bins", type=int, default=1 << 20)
+    ap.add_argument("--cpu-sample-bins", type=int, default=None,
+                    help="bins per sampled series the oracle timing covers (default 2^17 "
+                         "batched, 2^20 single series)")
+    ap.add_argument("--cpu-workers", type=int, default=None,
+                    help="oracle processes (default: usable cores, at most 16)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (for "
                          "scaling HBM byte counters) and exit")
-    return ap.parse_args()
+    return ap.parse_args(argv)
 
 
-def traffic_from_profiles(kernel: str, workload: str):
-    """HBM bytes per launch from the committed counter summary, if it was
-    taken on this exact kernel variant, workload and kernel source (else None)."""
-    from paper_1711_10855_amd.profile_summary import source_hash
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+def log(msg: str):
+    """Progress line on stderr (the JSON result is the only stdout line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def default_workers() -> int:
     try:
-        with open(path) as f:
-            rows = json.load(f)
-    except (OSError, ValueError):
-        return None
-    h = source_hash()
-    for row in rows:
-        if (row.get("kernel") == kernel and row.get("workload") == workload
-                and row.get("source_hash") == h):
-            return row.get("bytes_per_launch")
-    return None
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
 
 
-def cpu_baseline(a, zmax, dz, m, nz, sample_bins: int, checks=()):
-    """The FP64 oracle (unchanged) on the first `sample_bins` bins, all rows.
+# ---------------------------------------------------------------- oracle side
 
-    `checks`: (name, plane, first_row, row_step, bar) with `plane` the GPU
-    result's first `sample_bins` columns (rows first_row, first_row +
-    row_step, ... of the oracle's rows); each gets max |P - P_ref| / max P_ref
-    over the columns that do not depend on bins beyond the sample."""
-    import numpy as np
-
+def _oracle_bins(args):
+    """Worker: every row of the oracle plane over `count` bins starting at
+    offset `off` of the window `win` (the bins those outputs depend on, zero
+    outside the spectrum)."""
     import oracle
-    sample = np.ascontiguousarray(a[:sample_bins])
-    t0 = time.perf_counter()
-    p = oracle.plane_direct(sample, zmax, dz, m)
-    dt = time.perf_counter() - t0
-    pts = p.shape[0] * p.shape[1]
-    base = {"value": pts / dt, "unit": "points/s", "cores": 1, "kind": "oracle",
-            "sample": f"{nz} rows x first {sample_bins} bins of the input spectrum "
-                      f"({pts} points, {dt:.1f} s, single process NumPy FP64 direct sum)"}
-    errors = {}
-    ncol = sample_bins - m // 2
-    for name, plane, r0, step, bar in checks:
-        rows = plane.shape[0] // step
-        ref = p[r0:r0 + rows, :ncol]
-        got = plane[::step][:rows, :ncol].astype(np.float64)
-        err = float(np.max(np.abs(got - ref)) / np.max(ref))
-        errors[name] = {"max_abs_err_over_max_ref": err, "bar": bar, "pass": err <= bar,
-                        "points": int(ref.size),
-                        "sample": f"{rows} rows x first {ncol} bins, against the oracle above"}
-    return base, errors
+    key, c0, win, off, count, zmax, dz, m = args
+    p = oracle.plane_direct(win, zmax, dz, m)
+    return key, c0, p[:, off:off + count]
 
 
-def _time(fn, steps, warmup, stream):
+def _oracle_points(args):
+    """Worker: the oracle's direct sum at plane points (iz, r) of one series
+    of a batched workload, whose spectrum it draws again from the seeded
+    generator (the same call the GPU's input came from)."""
+    import oracle
+    from paper_1711_10855_amd import synth
+    key, name, spec, zmax, dz, m, iz, r = args
+    a = synth.batch_spectrum(name, spec) if spec is not None else [0j] * 4
+    return key, oracle.plane_points(a, zmax, dz, m, iz, r)
+
+
+class OraclePool:
+    """A process pool running the FP64 oracle (started fresh, so the workers
+    hold no GPU state)."""
+
+    def __init__(self, workers: int):
+        import multiprocessing as mp
+        self.workers = workers
+        self.pool = mp.get_context("spawn").Pool(workers)
+        # start every worker (imports included) before anything is timed
+        self.pool.map(_oracle_points, [(None, None, None, 0.0, 1.0, 2, [0], [0])] * workers,
+                      chunksize=1)
+
+    def dense(self, items, chunk=8192):
+        """items: (key, spectrum, zmax, dz, m, bins). Returns {key: plane of
+        every row x the first `bins` bins} and the wall time of the pool."""
+        import numpy as np
+        tasks = []
+        for key, a, zmax, dz, m, bins in items:
+            half = m // 2
+            for c0 in range(0, bins, chunk):
+                c1 = min(bins, c0 + chunk)
+                lo, hi = max(0, c0 - half), min(a.size, c1 + half)
+                tasks.append((key, c0, np.ascontiguousarray(a[lo:hi]), c0 - lo, c1 - c0,
+                              zmax, dz, m))
+        t0 = time.perf_counter()
+        parts = self.pool.map(_oracle_bins, tasks, chunksize=1)
+        dt = time.perf_counter() - t0
+        out = {}
+        for key, c0, p in parts:
+            out.setdefault(key, []).append((c0, p))
+        return {k: np.concatenate([p for _, p in sorted(v, key=lambda t: t[0])], axis=1)
+                for k, v in out.items()}, dt
+
+    def points(self, items):
+        """items: (key, workload name, series spec, zmax, dz, m, iz, r) ->
+        {key: P_ref at those points}."""
+        return dict(self.pool.map(_oracle_points, items, chunksize=1))
+
+    def close(self):
+        self.pool.close()
+        self.pool.join()
+
+
+def rel_error(got, ref) -> float:
+    """max |P - P_ref| / max P_ref over the compared points."""
+    import numpy as np
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return float(np.max(np.abs(got - ref)) / np.max(ref))
+
+
+def sample_points(nbins: int, rows: int, zmax_s: float, dz: float, chirps, seed: int, k: int):
+    """Plane points of one series checked against the oracle: the rows either
+    side of every injected signal's drift and r0 - 2 .. r0 + 2 (where the
+    largest powers are), the first and last two bins on the first, last and
+    a middle row, and k points uniform over the plane. Returns (iz, r)."""
+    import numpy as np
+    rng = np.random.default_rng(np.random.SeedSequence([171110855, 77, seed]))
+    iz, r = [], []
+    for c in chirps:
+        f = (c.z0 + zmax_s) / dz
+        for row in {int(math.floor(f)), int(math.ceil(f))}:
+            if 0 <= row < rows:
+                for d in range(-2, 3):
+                    rr = int(round(c.r0)) + d
+                    if 0 <= rr < nbins:
+                        iz.append(row)
+                        r.append(rr)
+    for row in {0, rows // 2, rows - 1}:
+        for rr in {0, 1, nbins - 2, nbins - 1}:
+            if 0 <= rr < nbins:
+                iz.append(row)
+                r.append(rr)
+    iz += rng.integers(0, rows, size=k).tolist()
+    r += rng.integers(0, nbins, size=k).tolist()
+    return np.asarray(iz, dtype=np.int64), np.asarray(r, dtype=np.int64)
+
+
+def pick_series(specs, count: int):
+    """Series the oracle timing (and the dense check) runs on: the shortest,
+    the longest, the first of each zmax, then those with the most injected
+    signals, up to `count`."""
+    order = list(range(len(specs)))
+    pick = [min(order, key=lambda i: specs[i].nbins), max(order, key=lambda i: specs[i].nbins)]
+    for z in sorted({s.zmax for s in specs}):
+        pick.append(next(i for i in order if specs[i].zmax == z))
+    pick += sorted(order, key=lambda i: (-len(specs[i].chirps), i))
+    out = []
+    for i in pick:
+        if i not in out:
+            out.append(i)
+    return out[:count]
+
+
+# ------------------------------------------------------------------- GPU side
+
+def _time(fn, steps, warmup, warmup_s, stream):
+    """Mean ms per call over `steps` calls bracketed by HIP events recorded on
+    `stream`, after `warmup` calls and at least `warmup_s` seconds of load."""
     import torch
+    t0 = time.perf_counter()
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
+    while time.perf_counter() - t0 < warmup_s:
+        fn()
+        torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
     start.record(stream)
     for _ in range(steps):
         fn()
     stop.record(stream)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    wall = time.perf_counter() - w0
     return start.elapsed_time(stop) / steps, wall
 
 
-def run_single(a_dev, zmax, dz, m, seg_len, prec, steps, warmup, flags=0, cand_thr=None,
-               keep_cols=0):
+def form_seg_len(form, w, args):
+    prec = FORMS[form][0]
+    if prec != "fp32":
+        return 4096
+    return args.seg_len or w.seg_len
+
+
+class Batch:
+    """A batched workload resident in device memory, with its waves."""
+
+    def __init__(self, name, nseries, wave_bytes, interbin):
+        import numpy as np
+        import torch
+
+        from paper_1711_10855_amd import synth
+        self.name = name
+        self.w = w = synth.WORKLOADS[name]
+        t0 = time.perf_counter()
+        self.specs, self.spectra = synth.batch_inputs(name, nseries)
+        self.gen_s = time.perf_counter() - t0
+        log(f"{name}: {len(self.specs)} series drawn in {self.gen_s:.1f} s")
+        dev = torch.device("cuda:0")
+        self.spec_dev = [torch.from_numpy(a).to(dev) for a in self.spectra]
+        per = 2 if interbin else 1
+        self.per = per
+        self.rows = [per * (int(round(2 * sp.zmax / w.dz)) + 1) for sp in self.specs]
+        # plane rows padded to 256-byte multiples (ld >= nbins), so that every
+        # row starts on a cache-line boundary
+        self.lds = [(sp.nbins + 63) // 64 * 64 for sp in self.specs]
+        sizes = [r * ld * 4 for r, ld in zip(self.rows, self.lds)]
+        waves, cur, acc = [], [], 0
+        for i, b in enumerate(sizes):
+            if cur and acc + b > wave_bytes:
+                waves.append(cur)
+                cur, acc = [], 0
+            cur.append(i)
+            acc += b
+        if cur:
+            waves.append(cur)
+        self.waves = waves
+        self.buf = torch.empty(max(sum(sizes[i] for i in wv) for wv in waves) // 4,
+                               dtype=torch.float32, device=dev)
+        self.calls = []
+        for wv in waves:
+            outs, off = [], 0
+            for i in wv:
+                plane = self.buf[off:off + self.rows[i] * self.lds[i]].view(self.rows[i],
+                                                                              self.lds[i])
+                outs.append(plane[:, :self.specs[i].nbins])
+                off += self.rows[i] * self.lds[i]
+            self.calls.append(([self.spec_dev[i] for i in wv],
+                               [self.specs[i].zmax for i in wv], outs))
+        self.points = int(sum(r * sp.nbins for r, sp in zip(self.rows, self.specs)))
+        self.nbins_total = int(sum(sp.nbins for sp in self.specs))
+        self.bytes_step = 4.0 * self.points + 8.0 * self.nbins_total
+        self.np = np
+
+    def run(self, plan, form, args, samples, dense_ids, dense_bins):
+        """Time one form; then run every wave once more and gather the sampled
+        plane points of every series (and the first bins of `dense_ids`)."""
+        import torch
+
+        def step():
+            for sp, zm, outs in self.calls:
+                plan.convolve_batch(sp, zm, outs)
+
+        stream = torch.cuda.current_stream(torch.device("cuda:0"))
+        ms, wall = _time(step, args.steps, args.warmup, args.warmup_s, stream)
+        info = plan.get_info()
+        got, dense = {}, {}
+        if samples is not None:
+            dev = torch.device("cuda:0")
+            for k, wv in enumerate(self.waves):
+                sp, zm, outs = self.calls[k]
+                plan.convolve_batch(sp, zm, outs)
+                torch.cuda.synchronize()
+                for j, i in enumerate(wv):
+                    iz, r = samples[i]
+                    it = torch.from_numpy(iz * self.per).to(dev)  # integer-bin rows
+                    rt = torch.from_numpy(r).to(dev)
+                    got[i] = outs[j][it, rt].cpu().numpy()
+                    if i in dense_ids:
+                        dense[i] = outs[j][::self.per, :dense_bins].cpu().numpy()
+        return {"ms": ms, "wall": wall, "info": info, "got": got, "dense": dense,
+                "value": self.points / (ms * 1e-3),
+                "achieved": self.bytes_step / (ms * 1e-3) / 1e9}
+
+
+def run_single(a_dev, zmax, dz, m, seg_len, prec, flags, args, keep_cols=0):
     """Time fdas_convolve (or the candidate epilogue) on one resident
-    spectrum; returns a result dict (with the plane's first `keep_cols`
-    columns, copied to the host after the timing, as "check")."""
+    spectrum; the plane's first `keep_cols` columns come back as "check"."""
     import torch
 
     from paper_1711_10855_amd import fdas
@@ -146,97 +362,258 @@ def run_single(a_dev, zmax, dz, m, seg_len, prec, steps, warmup, flags=0, cand_t
     nz, nbins = info.nz, a_dev.numel()
     stream = torch.cuda.current_stream(a_dev.device)
     ncand = None
-    if cand_thr is None:
+    if args.candidates is None:
         out = torch.empty((nz, nbins), dtype=torch.float32, device=a_dev.device)
-        ms, wall = _time(lambda: plan.convolve(a_dev, out=out), steps, warmup, stream)
+        ms, wall = _time(lambda: plan.convolve(a_dev, out=out), args.steps, args.warmup,
+                         args.warmup_s, stream)
         check = out[:, :keep_cols].cpu().numpy() if keep_cols else None
         del out
     else:
-        buf = plan.candidates(a_dev, cand_thr, capacity=1 << 20)
-        ms, wall = _time(lambda: plan.candidates(a_dev, cand_thr, buf=buf), steps, warmup, stream)
+        buf = plan.candidates(a_dev, args.candidates, capacity=1 << 20)
+        ms, wall = _time(lambda: plan.candidates(a_dev, args.candidates, buf=buf), args.steps,
+                         args.warmup, args.warmup_s, stream)
         ncand = int(buf[1].cpu()[0])
         check = None
     info = plan.get_info()  # templates per unit as the timed launches chose them
     plan.close()
     points = nz * nbins
-    bytes_launch = (4.0 * points if cand_thr is None else 16.0 * ncand) + 8.0 * nbins
+    bytes_launch = (4.0 * points if args.candidates is None else 16.0 * ncand) + 8.0 * nbins
     return {"points": points, "nz": nz, "nbins": nbins, "ms": ms, "wall": wall,
             "value": points / (ms * 1e-3), "bytes_launch": bytes_launch,
             "achieved": bytes_launch / (ms * 1e-3) / 1e9, "info": info, "ncand": ncand,
             "check": check}
 
 
-def run_batch(name, prec, seg_len, nseries, steps, warmup, wave_bytes, flags=0, keep_cols=0):
-    """Time fdas_convolve_batch over a batched workload, in waves that fit;
-    afterwards the wave holding the longest series runs once more and that
-    series' first `keep_cols` plane columns come back as "check"."""
+def traffic_from_profiles(kernel: str, workload: str):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on this exact kernel variant and workload and that kernel's sources
+    are unchanged since (else None)."""
+    from paper_1711_10855_amd.profile_summary import source_hash
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            rows = json.load(f)
+    except (OSError, ValueError):
+        return None
+    h = source_hash(kernel)
+    for row in rows:
+        if (row.get("kernel") == kernel and row.get("workload") == workload
+                and row.get("source_hash") == h):
+            return row.get("bytes_per_launch")
+    return None
+
+
+def arithmetic(form):
+    prec, flags = FORMS[form]
+    if prec == "fp32":
+        return "plain FP32"
+    return (f"{prec.upper()} storage, MFMA DFT stages, FP32 accumulation"
+            + (", hi+lo split products" if flags & SPLIT else ""))
+
+
+def dtype_of(form):
+    prec, flags = FORMS[form]
+    return "f32" if prec == "fp32" else f"{prec}{'x3' if flags & SPLIT else ''}+f32acc"
+
+
+# ------------------------------------------------------------------ workloads
+
+def bench_batch(args, forms, line):
     import numpy as np
+
+    from paper_1711_10855_amd import fdas
+    b = Batch(args.workload, args.nseries, int(args.wave_gb * 1e9), args.interbin)
+    w, specs = b.w, b.specs
+    ib = INTERBIN if args.interbin else 0
+    check = not args.no_check
+    samples = None
+    if check:
+        samples = {i: sample_points(sp.nbins, b.rows[i] // b.per, sp.zmax, w.dz, sp.chirps, i,
+                                    args.sample_points) for i, sp in enumerate(specs)}
+    n_dense = 8 if len({sp.zmax for sp in specs}) > 1 or len({sp.nbins for sp in specs}) > 1 else 4
+    dense_ids = pick_series(specs, n_dense) if check or not args.no_cpu_baseline else []
+    dense_bins = min(args.cpu_sample_bins or (1 << 17), min(specs[i].nbins for i in dense_ids)) \
+        if dense_ids else 0
+
+    results = {}
+    for form in forms:
+        prec, flags = FORMS[form]
+        seg_len = form_seg_len(form, w, args)
+        fl = flags | ib
+        if prec == "fp32" and args.workload == "batch-fp32" and not args.seg_len:
+            seg_len, fl = 0, fl | AUTOTUNE  # autotuned segment length (512 .. 8192)
+        plan = fdas.Plan(w.zmax, w.dz, w.m, seg_len, prec, fl, device=0)
+        log(f"{form}: plan {plan.info.kernel} L={plan.info.seg_len} "
+            f"({plan.info.plan_ms:.0f} ms); timing {len(b.waves)} waves x {args.steps} steps")
+        res = b.run(plan, form, args, samples, set(dense_ids) if check else set(), dense_bins)
+        plan.close()
+        results[form] = res
+        log(f"{form}: {res['ms']:.2f} ms per step, {res['value']:.4g} points/s, "
+            f"{res['achieved'] / HBM_PEAK_GBS:.3f} of HBM peak")
+
+    # oracle: sampled points of every series, dense first bins of a few, timed
+    pool = None
+    errors, base = {}, None
+    if check or not args.no_cpu_baseline:
+        pool = OraclePool(args.cpu_workers or default_workers())
+        log(f"oracle: {pool.workers} processes, dense series {dense_ids} x {dense_bins} bins")
+        dense_ref, dt = pool.dense([(i, b.spectra[i], specs[i].zmax, w.dz, w.m, dense_bins)
+                                    for i in dense_ids])
+        log(f"oracle: dense sample in {dt:.1f} s")
+        pts = sum(v.size for v in dense_ref.values())
+        if not args.no_cpu_baseline:
+            base = {"value": pts / dt, "unit": "points/s", "cores": pool.workers,
+                    "kind": "oracle",
+                    "sample": f"series {dense_ids}: every row x the first {dense_bins} bins "
+                              f"({pts} points, {dt:.1f} s), FP64 direct sum in "
+                              f"{pool.workers} processes over bin ranges"}
+        if check:
+            ref = pool.points([(i, args.workload, specs[i], specs[i].zmax, w.dz, w.m,
+                                *samples[i]) for i in range(len(specs))])
+            log(f"oracle: sampled points of {len(specs)} series")
+            ncol = dense_bins - w.m // 2
+            for form, res in results.items():
+                per = [rel_error(res["got"][i], ref[i]) for i in range(len(specs))]
+                dense = {int(i): rel_error(res["dense"][i][:, :ncol], dense_ref[i][:, :ncol])
+                         for i in dense_ids}
+                bar = bar_of(form)
+                worst = int(np.argmax(per))
+                errors[form] = {
+                    "max_abs_err_over_max_ref": max(max(per), max(dense.values())),
+                    "bar": bar,
+                    "pass": max(per) <= bar and max(dense.values()) <= bar,
+                    "series_passing": f"{sum(e <= bar for e in per)}/{len(per)}",
+                    "worst_series": worst,
+                    "per_series": [float(f"{e:.3g}") for e in per],
+                    "dense": {str(k): float(f"{v:.3g}") for k, v in dense.items()},
+                    "sample": f"per series: {args.sample_points} uniform plane points plus "
+                              "r0 +- 2 on the rows either side of each injected signal and "
+                              "both edges, max P_ref over those points; dense: every row x "
+                              f"the first {ncol} bins of the series listed"}
+        pool.close()
+
+    mixed = [f for f in forms if FORMS[f][0] != "fp32"]
+    ok = [f for f in mixed if not errors or errors[f]["pass"]]
+    pool_forms = ok or mixed or list(forms)
+    head = max(pool_forms, key=lambda f: results[f]["value"])
+    r = results[head]
+    info = r["info"]
+    fp32 = results.get("fp32")
+    line.update({
+        "value": r["value"], "ms_per_step": r["ms"], "dtype": dtype_of(head),
+        "config": {"workload": args.workload, "form": head, "nseries": len(specs),
+                   "waves": len(b.waves), "launches_per_step": len(b.waves),
+                   "points_per_step": b.points, "zmax": w.zmax, "dz": w.dz, "m": info.m,
+                   "seg_len": info.seg_len, "precision": FORMS[head][0],
+                   "arithmetic": arithmetic(head), "kernel": info.kernel,
+                   "templates_per_block": info.templates_per_block,
+                   "plan_ms": round(info.plan_ms, 3), "input_gen_s": round(b.gen_s, 1),
+                   "wall_s_timed": round(r["wall"], 4)},
+        "roofline": {"bound": "hbm", "achieved": r["achieved"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": r["achieved"] / HBM_PEAK_GBS,
+                     "traffic": traffic_from_profiles(info.kernel, args.workload),
+                     "bytes_per_point": b.bytes_step / b.points},
+    })
+    if fp32 is not None and head != "fp32":
+        line["speedup_vs_fp32"] = r["value"] / fp32["value"]
+    if args.interbin:
+        line["config"]["rows"] = "2 nz: integer and half-bin (r + 1/2) responses"
+    comp = {}
+    for f, res in results.items():
+        if f == head:
+            continue
+        comp[f] = {"value": res["value"], "ms_per_step": res["ms"], "kernel": res["info"].kernel,
+                   "seg_len": res["info"].seg_len, "arithmetic": arithmetic(f),
+                   "frac": res["achieved"] / HBM_PEAK_GBS,
+                   "plan_ms": round(res["info"].plan_ms, 3)}
+        if fp32 is not None and f != "fp32":
+            comp[f]["speedup_vs_fp32"] = res["value"] / fp32["value"]
+        if errors:
+            comp[f]["pass"] = errors[f]["pass"]
+    if comp:
+        line["compare"] = comp
+    line["cpu_baseline"] = base
+    if errors:
+        line["error_vs_oracle"] = errors
+
+
+def bench_single(args, forms, line):
     import torch
 
-    from paper_1711_10855_amd import fdas, synth
-    w = synth.WORKLOADS[name]
-    t0 = time.perf_counter()
-    specs, spectra = synth.batch_inputs(name, nseries)
-    gen_s = time.perf_counter() - t0
-    dev = torch.device("cuda:0")
-    spec_dev = [torch.from_numpy(a).to(dev) for a in spectra]
-    plan = fdas.Plan(w.zmax, w.dz, w.m, seg_len, prec, flags, device=0)
-    info = plan.info
-    per = 2 if flags & fdas.FLAG_INTERBIN else 1
-    rows = [per * (int(round(2 * sp.zmax / w.dz)) + 1) for sp in specs]
-    # plane rows padded to 256-byte multiples (ld >= nbins), so that every row
-    # starts on a cache-line boundary
-    lds = [(sp.nbins + 63) // 64 * 64 for sp in specs]
-    sizes = [r * ld * 4 for r, ld in zip(rows, lds)]
-    # waves: consecutive series whose planes fit the budget
-    waves, cur, acc = [], [], 0
-    for i, b in enumerate(sizes):
-        if cur and acc + b > wave_bytes:
-            waves.append(cur)
-            cur, acc = [], 0
-        cur.append(i)
-        acc += b
-    if cur:
-        waves.append(cur)
-    buf = torch.empty(max(sum(sizes[i] for i in wv) for wv in waves) // 4,
-                      dtype=torch.float32, device=dev)
-    calls = []
-    for wv in waves:
-        outs, off = [], 0
-        for i in wv:
-            plane = buf[off:off + rows[i] * lds[i]].view(rows[i], lds[i])
-            outs.append(plane[:, :specs[i].nbins])
-            off += rows[i] * lds[i]
-        calls.append(([spec_dev[i] for i in wv], [specs[i].zmax for i in wv], outs))
+    from paper_1711_10855_amd import synth
+    w = synth.WORKLOADS[args.workload]
+    src = "fp32-paper" if args.workload == "mixed-paper" else args.workload
+    a, _ = synth.single_series(src)
+    a_dev = torch.from_numpy(a).to("cuda:0")
+    ib = INTERBIN if args.interbin else 0
+    bins = min(args.cpu_sample_bins or (1 << 20), a.size)
+    keep = 0 if args.no_check else bins
+    results = {}
+    for form in forms:
+        prec, flags = FORMS[form]
+        results[form] = run_single(a_dev, w.zmax, w.dz, w.m, form_seg_len(form, w, args), prec,
+                                   flags | ib, args, keep_cols=keep)
+        log(f"{form}: {results[form]['ms']:.4f} ms per step")
+    head = forms[0]
+    r = results[head]
+    info = r["info"]
+    step = 2 if args.interbin else 1
+    line.update({
+        "value": r["value"], "ms_per_step": r["ms"], "dtype": dtype_of(head),
+        "config": {"workload": args.workload, "form": head, "nbins": r["nbins"], "nz": r["nz"],
+                   "zmax": w.zmax, "dz": w.dz, "m": info.m, "seg_len": info.seg_len,
+                   "precision": FORMS[head][0], "arithmetic": arithmetic(head),
+                   "kernel": info.kernel, "templates_per_block": info.templates_per_block,
+                   "plan_ms": round(info.plan_ms, 3), "wall_s_timed": round(r["wall"], 4)},
+        "roofline": {"bound": "hbm", "achieved": r["achieved"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": r["achieved"] / HBM_PEAK_GBS,
+                     "traffic": traffic_from_profiles(info.kernel, args.workload),
+                     "bytes_per_point": r["bytes_launch"] / r["points"]},
+    })
+    if args.interbin:
+        line["config"]["rows"] = "2 nz: integer and half-bin (r + 1/2) responses"
+    if args.candidates is not None:
+        line["config"]["epilogue"] = (f"threshold: points with power >= {args.candidates} "
+                                      f"listed, no plane written ({r['ncand']} found)")
+    comp = {}
+    for f, res in results.items():
+        if f == head:
+            continue
+        comp[f] = {"value": res["value"], "ms_per_step": res["ms"], "kernel": res["info"].kernel,
+                   "seg_len": res["info"].seg_len, "arithmetic": arithmetic(f),
+                   "frac": res["achieved"] / HBM_PEAK_GBS,
+                   "speedup_vs_" + head: res["value"] / r["value"]}
+    if comp:
+        line["compare"] = comp
+    if args.no_cpu_baseline and args.no_check:
+        return
+    pool = OraclePool(args.cpu_workers or default_workers())
+    ref, dt = pool.dense([(0, a, w.zmax, w.dz, w.m, bins)])
+    pool.close()
+    p = ref[0]
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = {
+            "value": p.size / dt, "unit": "points/s", "cores": pool.workers, "kind": "oracle",
+            "sample": f"every row x the first {bins} bins of the input spectrum ({p.size} "
+                      f"points, {dt:.1f} s), FP64 direct sum in {pool.workers} processes "
+                      "over bin ranges"}
+    errors = {}
+    ncol = bins - w.m // 2
+    for f, res in results.items():
+        if res["check"] is None:
+            continue
+        got = res["check"][::step][:, :ncol]
+        err = rel_error(got, p[:got.shape[0], :ncol])
+        errors[f] = {"max_abs_err_over_max_ref": err, "bar": bar_of(f),
+                     "pass": err <= bar_of(f), "points": int(got.size),
+                     "sample": f"{got.shape[0]} rows x first {ncol} bins, against the "
+                               "oracle above"}
+    if errors:
+        line["error_vs_oracle"] = errors
 
-    def step():
-        for sp, zm, outs in calls:
-            plan.convolve_batch(sp, zm, outs)
 
-    stream = torch.cuda.current_stream(dev)
-    ms, wall = _time(step, steps, warmup, stream)
-    i0 = int(np.argmax([sp.nbins for sp in specs]))
-    check = None
-    if keep_cols:
-        for k, wv in enumerate(waves):
-            if i0 in wv:
-                sp, zm, outs = calls[k]
-                plan.convolve_batch(sp, zm, outs)
-                check = outs[wv.index(i0)][:, :keep_cols].cpu().numpy()
-    plan.close()
-    points = int(sum(r * sp.nbins for r, sp in zip(rows, specs)))
-    nbins_total = int(sum(sp.nbins for sp in specs))
-    bytes_launch = 4.0 * points + 8.0 * nbins_total
-    a0 = spectra[i0]
-    return {"points": points, "nseries": len(specs), "waves": len(waves), "ms": ms,
-            "wall": wall, "value": points / (ms * 1e-3), "bytes_launch": bytes_launch,
-            "achieved": bytes_launch / (ms * 1e-3) / 1e9, "info": info, "gen_s": gen_s,
-            "sample_spectrum": a0, "zmax": w.zmax, "dz": w.dz, "m": w.m, "check": check,
-            "check_first_row": int(round((w.zmax - specs[i0].zmax) / w.dz))}
-
-
-def main():
-    args = parse()
+def main(argv=None):
+    args = parse(argv)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
@@ -246,9 +623,23 @@ def main():
     if args.zpb:
         os.environ["FDAS_ZPB"] = str(args.zpb)
 
+    from paper_1711_10855_amd import synth
+    if args.workload not in synth.WORKLOADS:
+        print(json.dumps({"error": f"unknown workload {args.workload}"}))
+        sys.exit(2)
+    batched = synth.WORKLOADS[args.workload].nseries > 1
+    forms = (args.forms or DEFAULT_FORMS["batch" if batched else "single"]).split(",")
+    bad = [f for f in forms if f not in FORMS]
+    if bad or not forms:
+        print(json.dumps({"error": f"unknown forms {bad}; known: {list(FORMS)}"}))
+        sys.exit(2)
+    if args.candidates is not None and batched:
+        print(json.dumps({"error": "--candidates applies to single-series workloads"}))
+        sys.exit(2)
+
     import torch
 
-    from paper_1711_10855_amd import fdas, synth
+    from paper_1711_10855_amd import fdas
 
     if args.calibrate_copy:
         n = args.calibrate_copy << 20
@@ -262,90 +653,18 @@ def main():
 
     fdas.load()
     torch.cuda.set_device(0)
-    w = synth.WORKLOADS[args.workload]
-    prec = args.precision or w.precision
-    if args.split and prec == "fp32":
-        print(json.dumps({"error": "--split applies to the mixed precisions only"}))
-        sys.exit(2)
-    flags = (fdas.FLAG_SPLIT if args.split else 0) | (fdas.FLAG_INTERBIN if args.interbin else 0)
-    compare = None
-    keep = 0 if args.no_cpu_baseline else args.cpu_sample_bins
-    bar = 1e-4 if prec == "fp32" else 1e-3
-    if w.nseries == 1:
-        seg_len = args.seg_len or (4096 if prec != "fp32" else w.seg_len)
-        src = "fp32-paper" if args.workload == "mixed-paper" else args.workload
-        a, _ = synth.single_series(src)
-        a_dev = torch.from_numpy(a).to("cuda:0")
-        r = run_single(a_dev, w.zmax, w.dz, w.m, seg_len, prec, args.steps, args.warmup, flags,
-                       args.candidates, keep_cols=min(keep, a.size))
-        step = 2 if args.interbin else 1  # integer-bin rows only
-        checks = [] if r["check"] is None else [(prec, r["check"], 0, step, bar)]
-        if not args.no_compare and prec == "fp32" and not args.variant and w.m < 4096:
-            c = run_single(a_dev, w.zmax, w.dz, w.m, 4096, "fp16", args.steps, args.warmup,
-                           flags & fdas.FLAG_INTERBIN, args.candidates,
-                           keep_cols=min(keep, a.size))
-            compare = {"fp16_mfma": {
-                "value": c["value"], "ms_per_step": c["ms"], "seg_len": 4096,
-                "kernel": c["info"].kernel, "frac": c["achieved"] / HBM_PEAK_GBS,
-                "speedup_vs_fp32": c["value"] / r["value"],
-                "error_bar": "max|P-P_ref| <= 1e-3 max P_ref"}}
-            if c["check"] is not None:
-                checks.append(("fp16_mfma", c["check"], 0, step, 1e-3))
-        cpu_in = (a, w.zmax, w.dz, w.m, r["nz"] // step)
-        cfg = {"workload": args.workload, "nbins": r["nbins"], "nz": r["nz"]}
-    else:
-        seg_len = args.seg_len or (4096 if prec != "fp32" else w.seg_len)
-        r = run_batch(args.workload, prec, seg_len, args.nseries, args.steps, args.warmup,
-                      int(args.wave_gb * 1e9), flags, keep_cols=keep)
-        step = 2 if args.interbin else 1
-        checks = [] if r["check"] is None else [
-            (f"{prec} (longest series)", r["check"], r["check_first_row"], step, bar)]
-        cpu_in = (r["sample_spectrum"], r["zmax"], r["dz"], r["m"], r["info"].nz // step)
-        cfg = {"workload": args.workload, "nseries": r["nseries"], "waves": r["waves"],
-               "input_gen_s": round(r["gen_s"], 1)}
-    info = r["info"]
-    cfg.update({"m": info.m, "seg_len": info.seg_len, "zmax": w.zmax, "dz": w.dz,
-                "precision": prec, "kernel": info.kernel,
-                "templates_per_block": info.templates_per_block,
-                "plan_ms": round(info.plan_ms, 3), "wall_s_timed": round(r["wall"], 4)})
-    traffic = traffic_from_profiles(info.kernel, args.workload)
-    cfg["arithmetic"] = ("plain FP32" if prec == "fp32"
-                         else f"{prec} storage, MFMA DFT stages, FP32 accumulation"
-                         + (", hi+lo split products" if args.split else ""))
-    if args.interbin:
-        cfg["rows"] = "2 nz: integer and half-bin (r + 1/2) responses"
-    if args.candidates is not None:
-        cfg["epilogue"] = (f"threshold: points with power >= {args.candidates} listed, "
-                           f"no plane written ({r.get('ncand')} found)")
     line = {
-        "metric": "z\u2013r plane points/s, batched mixed-precision vs plain FP32; "
+        "metric": "z–r plane points/s, batched mixed-precision vs plain FP32; "
                   "% of HBM roofline",
-        "value": r["value"],
-        "unit": "points/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": r["ms"],
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32" if prec == "fp32" else f"{prec}{'x3' if args.split else ''}+f32acc",
-        "data": "synthetic",
-        "config": cfg,
-        "roofline": {"bound": "hbm", "achieved": r["achieved"], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": r["achieved"] / HBM_PEAK_GBS, "traffic": traffic,
-                     "bytes_per_point": r["bytes_launch"] / r["points"]},
-        "cpu_baseline": None,
+        "value": None, "unit": "points/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": None, "data": "synthetic",
+        "config": {}, "roofline": None, "cpu_baseline": None,
     }
-    if compare:
-        line["compare"] = compare
-    if not args.no_cpu_baseline:
-        a0, zmax, dz, m, nz = cpu_in
-        base, errors = cpu_baseline(a0, zmax, dz, m, nz, min(args.cpu_sample_bins, a0.size),
-                                    checks)
-        line["cpu_baseline"] = base
-        if errors:
-            line["error_vs_oracle"] = errors
+    if batched:
+        bench_batch(args, forms, line)
+    else:
+        bench_single(args, forms, line)
     print(json.dumps(line))
 
 

@@ -179,8 +179,41 @@ __global__ void tune_fill_kernel(c32 *spec, int64_t n) {
   if (i < n) spec[i] = {1.0f + 1e-3f * (float)(i & 1023), 0.5f - 1e-3f * (float)(i & 511)};
 }
 
+// Median of `reps` timed calls of one candidate plan, each bracketed by its
+// own pair of events, after `warm` untimed calls.
+static int time_candidate(fdas_plan_t pl, const void *spec, int64_t nbins, float *power,
+                          hipStream_t s, hipEvent_t *ev, int warm, int reps, float *median_ms) {
+  int st = FDAS_OK;
+  for (int r = 0; r < warm && st == FDAS_OK; ++r) st = plan_convolve(pl, spec, nbins, power, nbins, s);
+  for (int r = 0; r < reps && st == FDAS_OK; ++r) {
+    (void)hipEventRecord(ev[2 * r], s);
+    st = plan_convolve(pl, spec, nbins, power, nbins, s);
+    (void)hipEventRecord(ev[2 * r + 1], s);
+  }
+  if (st != FDAS_OK) return st;
+  hipError_t e = hipEventSynchronize(ev[2 * reps - 1]);
+  if (e != hipSuccess) return hip_error(e, "autotune timing");
+  std::vector<float> ms(reps);
+  for (int r = 0; r < reps; ++r) {
+    e = hipEventElapsedTime(&ms[r], ev[2 * r], ev[2 * r + 1]);
+    if (e != hipSuccess) return hip_error(e, "autotune timing");
+  }
+  std::sort(ms.begin(), ms.end());
+  *median_ms = ms[reps / 2];
+  return FDAS_OK;
+}
+
+// Autotuner: every compiled variant of the precision and split form, at
+// every admissible segment length (L - m >= L/2 unless the caller fixed L),
+// with the plan's own per-launch choice of templates per unit and with a
+// few fixed group sizes, is timed on a synthetic 2^20-bin spectrum; the
+// fastest per plane point wins. The GPU is first kept busy for a fixed time
+// so that its clock has settled before anything is compared; each candidate
+// then takes the median of several individually timed calls.
 static int autotune(const fdas_params &p, int nz, int device, hipStream_t s, TuneChoice *best) {
   const int64_t nbins = (int64_t)1 << 20;
+  constexpr int kReps = 7;
+  constexpr double kHeatMs = 100.0;
   void *spec = nullptr;
   float *power = nullptr;
   hipError_t e = hipMalloc(&spec, nbins * 8);
@@ -191,10 +224,10 @@ static int autotune(const fdas_params &p, int nz, int device, hipStream_t s, Tun
   }
   hipLaunchKernelGGL(tune_fill_kernel, dim3((unsigned)((nbins + 255) / 256)), dim3(256), 0, s,
                      static_cast<c32 *>(spec), nbins);
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  (void)hipEventCreate(&e0);
-  (void)hipEventCreate(&e1);
+  hipEvent_t ev[2 * kReps] = {};
+  for (auto &x : ev) (void)hipEventCreate(&x);
   int status = FDAS_OK;
+  bool heated = false;
   best->var = nullptr;
   for (int pass = 0; pass < 2 && status == FDAS_OK; ++pass) {
     int n = 0;
@@ -203,11 +236,14 @@ static int autotune(const fdas_params &p, int nz, int device, hipStream_t s, Tun
       const OlsVariant *v = &vs[i];
       if (v->precision != p.precision || v->split != plan_split(p)) continue;
       if (p.seg_len ? v->L != p.seg_len : (v->L - p.m) * 2 < v->L) continue;
-      int last_zpb = -1;
+      // zpb 0: the plan's own choice (units of the variant's target size, or
+      // per launch from the grid's rounds); then fixed near-equal groups
+      std::vector<int> cands = {0};
       for (int ng : {1, 2, 3, 4, 6, 8, 12}) {
         const int zpb = (nz + ng - 1) / ng;
-        if (zpb == last_zpb) continue;
-        last_zpb = zpb;
+        if (std::find(cands.begin(), cands.end(), zpb) == cands.end()) cands.push_back(zpb);
+      }
+      for (int zpb : cands) {
         fdas_params q = p;
         q.seg_len = v->L;
         fdas_plan_t pl = nullptr;
@@ -216,22 +252,26 @@ static int autotune(const fdas_params &p, int nz, int device, hipStream_t s, Tun
           status = st;
           break;
         }
-        st = plan_convolve(pl, spec, nbins, power, nbins, s);  // warm-up
-        if (st == FDAS_OK) (void)hipEventRecord(e0, s);
-        for (int r = 0; r < 3 && st == FDAS_OK; ++r) st = plan_convolve(pl, spec, nbins, power, nbins, s);
-        float ms = 0.f;
-        if (st == FDAS_OK) {
-          (void)hipEventRecord(e1, s);
-          e = hipEventSynchronize(e1);
-          if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-          if (e != hipSuccess) st = hip_error(e, "autotune timing");
+        if (!heated) {  // settle the clock before the first comparison
+          const auto t0 = std::chrono::steady_clock::now();
+          while (st == FDAS_OK &&
+                 std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
+                         .count() < kHeatMs) {
+            for (int r = 0; r < 8 && st == FDAS_OK; ++r)
+              st = plan_convolve(pl, spec, nbins, power, nbins, s);
+            e = hipStreamSynchronize(s);
+            if (st == FDAS_OK && e != hipSuccess) st = hip_error(e, "autotune warm-up");
+          }
+          heated = true;
         }
+        float ms = 0.f;
+        if (st == FDAS_OK) st = time_candidate(pl, spec, nbins, power, s, ev, 2, kReps, &ms);
         destroy_plan(pl);
         if (st != FDAS_OK) {
           status = st;
           break;
         }
-        const double ns = (double)ms * 1e6 / 3.0 / ((double)nz * (double)nbins);
+        const double ns = (double)ms * 1e6 / ((double)nz * (double)nbins);
         if (!best->var || ns < best->ns_per_point) {
           best->var = v;
           best->L = v->L;
@@ -241,8 +281,7 @@ static int autotune(const fdas_params &p, int nz, int device, hipStream_t s, Tun
       }
     }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  for (auto &x : ev) (void)hipEventDestroy(x);
   (void)hipFree(spec);
   (void)hipFree(power);
   if (status == FDAS_OK && !best->var)

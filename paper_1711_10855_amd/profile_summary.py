@@ -24,17 +24,26 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-KERNEL_SOURCES = ["csrc/ols_fp32.hip", "csrc/fft_radix.hpp", "csrc/fft_block.hpp",
-                  "csrc/ols_mixed.hip", "csrc/ols_variants.hpp"]
+# Sources each hot kernel is built from: a traffic row stays current only
+# while the sources of its own kernel are unchanged.
+FP32_SOURCES = ["csrc/ols_fp32.hip", "csrc/fft_radix.hpp", "csrc/fft_block.hpp",
+                "csrc/layout.hpp", "csrc/ols_variants.hpp"]
+MIXED_SOURCES = ["csrc/ols_mixed.hip", "csrc/fft_radix.hpp", "csrc/ols_variants.hpp"]
 
 
-def source_hash() -> str:
-    """Hash of the hot-kernel sources; a traffic row is current only while
-    these files are unchanged."""
+def kernel_sources(kernel: str) -> list[str]:
+    """Source files of a hot-kernel variant, by its name (fp32_* variants are
+    the FP32 kernels, the others the matrix-core kernels)."""
+    return FP32_SOURCES if kernel.startswith("fp32_") else MIXED_SOURCES
+
+
+def source_hash(kernel: str) -> str:
+    """Hash of the sources of the named kernel variant."""
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in kernel_sources(kernel):
         p = os.path.join(HERE, rel)
         if os.path.exists(p):
+            h.update(rel.encode())
             h.update(open(p, "rb").read())
     return h.hexdigest()[:16]
 
@@ -133,7 +142,7 @@ def main():
                          f"traffic / algorithmic = {tb/a.bytes_per_launch:.3f}")
         lines.append("")
         row = {"kernel": a.variant, "workload": a.workload, "bytes_per_launch": tb,
-               "source_hash": source_hash(), "profile": a.name}
+               "source_hash": source_hash(a.variant), "profile": a.name}
     if avg_ns:
         lines.append(f"Average duration of the hot kernel under the profiler: {avg_ns/1e3:.1f} us")
     tr = _one(os.path.join(d, "prof_kt", "*kernel_trace.csv"))
