@@ -199,6 +199,24 @@ int fdas_convolve_candidates(fdas_plan_t plan, const void *spectrum, int64_t nbi
 int fdas_convolve_batch(fdas_plan_t plan, const fdas_series *series,
                         int nseries, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the batched
+ * hot path of fdas_convolve_batch with the same work items, kernels and
+ * results, but no allocation, no graph and no host synchronisation. The
+ * descriptor table (56 bytes per series) and the work counter live in a
+ * device array of the library, one per GPU, FDAS_NOALLOC_SCRATCH_BYTES
+ * (229,632) bytes, held until the process ends; descriptors reach it as kernel
+ * arguments, so `series` may be reused as soon as the call returns.
+ *   nseries : 1 .. FDAS_NOALLOC_MAX_SERIES; more is FDAS_ERR_INVALID.
+ * Other arguments, validation and errors are those of fdas_convolve_batch.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (different streams, or different threads without ordering) race and
+ * must not be made; calls ordered on one stream are safe.                   */
+#define FDAS_NOALLOC_MAX_SERIES 4096
+#define FDAS_NOALLOC_SCRATCH_BYTES (FDAS_NOALLOC_MAX_SERIES * 56 + 256)
+int fdas_convolve_batch_noalloc(fdas_plan_t plan, const fdas_series *series, int nseries,
+                                void *stream);
+
 /* Release a plan and everything it owns. NULL is allowed (returns FDAS_OK).
  * Synchronises the device the plan lives on.                                */
 int fdas_destroy(fdas_plan_t plan);

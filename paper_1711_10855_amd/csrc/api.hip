@@ -289,7 +289,8 @@ int fdas_convolve_candidates(fdas_plan_t plan, const void *spectrum, int64_t nbi
                                   (hipStream_t)stream);
 }
 
-int fdas_convolve_batch(fdas_plan_t plan, const fdas_series *series, int nseries, void *stream) {
+// Argument checks shared by the two batched entry points (host only).
+static int check_batch(fdas_plan_t plan, const fdas_series *series, int nseries) {
   if (!plan) return set_error(FDAS_ERR_INVALID, "null plan");
   if (!series || nseries < 1) return set_error(FDAS_ERR_INVALID, "need nseries >= 1 and a series array");
   for (int i = 0; i < nseries; ++i) {
@@ -300,9 +301,27 @@ int fdas_convolve_batch(fdas_plan_t plan, const fdas_series *series, int nseries
     if ((reinterpret_cast<uintptr_t>(s.spectrum) & 7) || (reinterpret_cast<uintptr_t>(s.power) & 3))
       return set_error(FDAS_ERR_INVALID, "series %d: misaligned pointer", i);
   }
+  return FDAS_OK;
+}
+
+int fdas_convolve_batch(fdas_plan_t plan, const fdas_series *series, int nseries, void *stream) {
+  const int st = check_batch(plan, series, nseries);
+  if (st != FDAS_OK) return st;
   DeviceGuard guard(plan_device(plan));
   if (guard.err != hipSuccess) return hip_error(guard.err, "hipSetDevice");
   return plan_convolve_batch(plan, series, nseries, (hipStream_t)stream);
+}
+
+int fdas_convolve_batch_noalloc(fdas_plan_t plan, const fdas_series *series, int nseries,
+                                void *stream) {
+  const int st = check_batch(plan, series, nseries);
+  if (st != FDAS_OK) return st;
+  if (nseries > FDAS_NOALLOC_MAX_SERIES)
+    return set_error(FDAS_ERR_INVALID, "%d series exceed FDAS_NOALLOC_MAX_SERIES (%d)", nseries,
+                     FDAS_NOALLOC_MAX_SERIES);
+  DeviceGuard guard(plan_device(plan));
+  if (guard.err != hipSuccess) return hip_error(guard.err, "hipSetDevice");
+  return plan_convolve_batch_noalloc(plan, series, nseries, (hipStream_t)stream);
 }
 
 int fdas_destroy(fdas_plan_t plan) {

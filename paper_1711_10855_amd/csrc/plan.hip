@@ -12,6 +12,7 @@
 #include <string>
 #include <vector>
 
+#include "noalloc.hpp"
 #include "plan.hpp"
 
 struct fdas_plan_s {
@@ -515,6 +516,66 @@ int plan_convolve_candidates(fdas_plan_t pl, const void *spec, int64_t nbins, fl
   return plan_launch(pl, spec, nbins, nullptr, 0, cd, s);
 }
 
+// One series of a batch: check its zmax against the plan's z grid and fill
+// its descriptor (all but the first work item); `cost` orders the series.
+static int series_desc(fdas_plan_t pl, const fdas_series &x, int i, SeriesDesc *d,
+                       double *cost) {
+  const double dz = pl->p.dz;
+  if (!std::isfinite(x.zmax) || x.zmax < 0.0 || x.zmax > pl->p.zmax * (1.0 + 1e-12) + 1e-12)
+    return set_error(FDAS_ERR_INVALID, "series %d: zmax %g outside [0, %g]", i, x.zmax, pl->p.zmax);
+  const double off = (pl->p.zmax - x.zmax) / dz;
+  const double span = 2.0 * x.zmax / dz;
+  if (std::fabs(off - std::nearbyint(off)) > 1e-9 || std::fabs(span - std::nearbyint(span)) > 1e-9)
+    return set_error(FDAS_ERR_INVALID, "series %d: zmax %g is not on the plan's z grid", i, x.zmax);
+  const int64_t nseg = (x.nbins + pl->U - 1) / pl->U;
+  if (nseg > INT_MAX / 2) return set_error(FDAS_ERR_UNSUPPORTED, "series %d too long", i);
+  const int per = (pl->p.flags & FDAS_FLAG_INTERBIN) ? 2 : 1;  // bank rows per drift
+  d->spec = x.spectrum;
+  d->power = x.power;
+  d->nbins = x.nbins;
+  d->ld = x.ld;
+  d->item_begin = 0;
+  d->nseg = (int)nseg;
+  d->nz = per * ((int)std::nearbyint(span) + 1);
+  d->row_off = per * (int)std::nearbyint(off);
+  // near-equal template groups of at most the plan's templates per unit
+  const int ng = (d->nz + pl->zpb - 1) / pl->zpb;
+  d->zpb = (d->nz + ng - 1) / ng;
+  *cost = (double)d->nz * (double)x.nbins;
+  return FDAS_OK;
+}
+
+static int64_t series_items(const SeriesDesc &d, int G) {
+  const int64_t nsb = (d.nseg + G - 1) / G;
+  const int64_t nzg = (d.nz + d.zpb - 1) / d.zpb;
+  return nsb * nzg;
+}
+
+// Launch arguments of the batch kernel over a descriptor table on the device.
+static int batch_args(fdas_plan_t pl, const SeriesDesc *d_desc, int nseries, int64_t total,
+                      unsigned long long *counter, BatchArgs *a) {
+  if (!pl->cus) {
+    const hipError_t e =
+        hipDeviceGetAttribute(&pl->cus, hipDeviceAttributeMultiprocessorCount, pl->device);
+    if (e != hipSuccess) return hip_error(e, "CU count");
+  }
+  const int per_cu = std::max(1, pl->var->batch_blocks_per_cu());
+  a->desc = d_desc;
+  a->nseries = nseries;
+  a->total = total;
+  a->counter = counter;
+  a->bank = pl->bank;
+  a->tw = pl->tw;
+  a->U = pl->U;
+  a->half = pl->m / 2;
+  a->zpb = pl->zpb;
+  a->grid = (int)std::min<int64_t>((int64_t)pl->cus * per_cu, total);
+  a->bank_log2 = 0;
+  while ((1 << a->bank_log2) < pl->L) ++a->bank_log2;
+  a->consts = pl->consts;
+  return FDAS_OK;
+}
+
 // Host side of the batched path: validate and order the series (largest
 // first), lay out their work items, upload the descriptors when the batch
 // changes, and replay one captured graph of the batch launch.
@@ -522,32 +583,11 @@ int plan_convolve_batch(fdas_plan_t pl, const fdas_series *series, int nseries, 
   if (!pl->var->launch_batch)
     return set_error(FDAS_ERR_UNSUPPORTED, "kernel %s has no batched form", pl->var->name);
   const int G = pl->var->G;
-  const double dz = pl->p.dz;
   std::vector<SeriesDesc> desc(nseries);
   std::vector<double> cost(nseries);
   for (int i = 0; i < nseries; ++i) {
-    const fdas_series &x = series[i];
-    if (!std::isfinite(x.zmax) || x.zmax < 0.0 || x.zmax > pl->p.zmax * (1.0 + 1e-12) + 1e-12)
-      return set_error(FDAS_ERR_INVALID, "series %d: zmax %g outside [0, %g]", i, x.zmax, pl->p.zmax);
-    const double off = (pl->p.zmax - x.zmax) / dz;
-    const double span = 2.0 * x.zmax / dz;
-    if (std::fabs(off - std::nearbyint(off)) > 1e-9 || std::fabs(span - std::nearbyint(span)) > 1e-9)
-      return set_error(FDAS_ERR_INVALID, "series %d: zmax %g is not on the plan's z grid", i, x.zmax);
-    const int64_t nseg = (x.nbins + pl->U - 1) / pl->U;
-    if (nseg > INT_MAX / 2) return set_error(FDAS_ERR_UNSUPPORTED, "series %d too long", i);
-    SeriesDesc &d = desc[i];
-    const int per = (pl->p.flags & FDAS_FLAG_INTERBIN) ? 2 : 1;  // bank rows per drift
-    d.spec = x.spectrum;
-    d.power = x.power;
-    d.nbins = x.nbins;
-    d.ld = x.ld;
-    d.nseg = (int)nseg;
-    d.nz = per * ((int)std::nearbyint(span) + 1);
-    d.row_off = per * (int)std::nearbyint(off);
-    // near-equal template groups of at most the plan's templates per unit
-    const int ng = (d.nz + pl->zpb - 1) / pl->zpb;
-    d.zpb = (d.nz + ng - 1) / ng;
-    cost[i] = (double)d.nz * (double)x.nbins;
+    const int st = series_desc(pl, series[i], i, &desc[i], &cost[i]);
+    if (st != FDAS_OK) return st;
   }
   std::vector<int> order(nseries);
   std::iota(order.begin(), order.end(), 0);
@@ -557,9 +597,7 @@ int plan_convolve_batch(fdas_plan_t pl, const fdas_series *series, int nseries, 
   for (int k = 0; k < nseries; ++k) {
     sorted[k] = desc[order[k]];
     sorted[k].item_begin = total;
-    const int64_t nsb = (sorted[k].nseg + G - 1) / G;
-    const int64_t nzg = (sorted[k].nz + sorted[k].zpb - 1) / sorted[k].zpb;
-    total += nsb * nzg;
+    total += series_items(sorted[k], G);
   }
   if (total == 0) return FDAS_OK;
 
@@ -601,28 +639,12 @@ int plan_convolve_batch(fdas_plan_t pl, const fdas_series *series, int nseries, 
         return hip_error(e, "capture stream");
       }
     }
-    if (!pl->cus) {
-      e = hipDeviceGetAttribute(&pl->cus, hipDeviceAttributeMultiprocessorCount, pl->device);
-      if (e != hipSuccess) {
-        (void)hipFree(ent.d_desc);
-        return hip_error(e, "CU count");
-      }
-    }
-    const int per_cu = std::max(1, pl->var->batch_blocks_per_cu());
     BatchArgs a;
-    a.desc = ent.d_desc;
-    a.nseries = nseries;
-    a.total = total;
-    a.counter = pl->counter;
-    a.bank = pl->bank;
-    a.tw = pl->tw;
-    a.U = pl->U;
-    a.half = pl->m / 2;
-    a.zpb = pl->zpb;
-    a.grid = (int)std::min<int64_t>((int64_t)pl->cus * per_cu, total);
-    a.bank_log2 = 0;
-    while ((1 << a.bank_log2) < pl->L) ++a.bank_log2;
-    a.consts = pl->consts;
+    const int st = batch_args(pl, ent.d_desc, nseries, total, pl->counter, &a);
+    if (st != FDAS_OK) {
+      (void)hipFree(ent.d_desc);
+      return st;
+    }
     if (eager) {
       e = pl->var->launch_batch(a, s);
       hipError_t e2 = hipStreamSynchronize(s);
@@ -657,6 +679,61 @@ int plan_convolve_batch(fdas_plan_t pl, const fdas_series *series, int nseries, 
   hit->last_use = ++pl->use_clock;
   e = hipGraphLaunch(hit->exec, s);
   if (e != hipSuccess) return hip_error(e, "graph launch");
+  return FDAS_OK;
+}
+
+// Allocation-free batched path: the same work items and kernels, with the
+// descriptor table and the work counter in the library's device scratch
+// array (uploaded as kernel arguments) and the launch made directly on the
+// stream, without a graph. Host-side state is on the stack.
+int plan_convolve_batch_noalloc(fdas_plan_t pl, const fdas_series *series, int nseries,
+                                hipStream_t s) {
+  if (!pl->var->launch_batch)
+    return set_error(FDAS_ERR_UNSUPPORTED, "kernel %s has no batched form", pl->var->name);
+  if (nseries > kNoAllocMaxSeries)
+    return set_error(FDAS_ERR_INVALID, "%d series exceed the %d the allocation-free batch holds",
+                     nseries, kNoAllocMaxSeries);
+  const int G = pl->var->G;
+  double cost[kNoAllocMaxSeries];
+  int order[kNoAllocMaxSeries];
+  for (int i = 0; i < nseries; ++i) {
+    SeriesDesc d;
+    const int st = series_desc(pl, series[i], i, &d, &cost[i]);
+    if (st != FDAS_OK) return st;
+    order[i] = i;
+  }
+  // largest first, ties in input order (the order the graph path uses)
+  std::sort(order, order + nseries,
+            [&](int a, int b) { return cost[a] > cost[b] || (cost[a] == cost[b] && a < b); });
+  void *base = nullptr;
+  int st = noalloc_scratch(pl->device, &base);
+  if (st != FDAS_OK) return st;
+  SeriesDesc *table = static_cast<SeriesDesc *>(base);
+  unsigned long long *counter =
+      reinterpret_cast<unsigned long long *>(static_cast<unsigned char *>(base) + kNoAllocDescBytes);
+  DescChunk chunk;
+  chunk.n = 0;
+  chunk.first = 0;
+  int64_t total = 0;
+  for (int k = 0; k < nseries; ++k) {
+    SeriesDesc &d = chunk.d[chunk.n];
+    double c = 0.0;
+    (void)series_desc(pl, series[order[k]], order[k], &d, &c);
+    d.item_begin = total;
+    total += series_items(d, G);
+    if (++chunk.n == kDescChunk || k == nseries - 1) {
+      const hipError_t e = launch_desc_upload(chunk, table, s);
+      if (e != hipSuccess) return hip_error(e, "descriptor upload kernel");
+      chunk.first += chunk.n;
+      chunk.n = 0;
+    }
+  }
+  if (total == 0) return FDAS_OK;
+  BatchArgs a;
+  st = batch_args(pl, table, nseries, total, counter, &a);
+  if (st != FDAS_OK) return st;
+  const hipError_t e = pl->var->launch_batch(a, s);
+  if (e != hipSuccess) return hip_error(e, "batch kernel launch");
   return FDAS_OK;
 }
 

@@ -24,6 +24,8 @@ int plan_bank_natural(fdas_plan_t plan, void *dst, hipStream_t s);
 int plan_convolve(fdas_plan_t plan, const void *spec, int64_t nbins, float *power, int64_t ld,
                   hipStream_t s);
 int plan_convolve_batch(fdas_plan_t plan, const fdas_series *series, int nseries, hipStream_t s);
+int plan_convolve_batch_noalloc(fdas_plan_t plan, const fdas_series *series, int nseries,
+                                hipStream_t s);
 int plan_convolve_candidates(fdas_plan_t plan, const void *spec, int64_t nbins, float thr,
                              void *cands, int64_t cap, unsigned long long *count, hipStream_t s);
 int destroy_plan(fdas_plan_t plan);

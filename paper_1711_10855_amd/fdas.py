@@ -37,7 +37,7 @@ EXPORTS = (
     "fdas_destroy", "fdas_status_string", "fdas_last_error", "fdas_kernel_variants",
     "fdas_convolve_candidates", "fdas_fft_plan", "fdas_fft_get_info", "fdas_fft_exec",
     "fdas_fft_destroy", "fdas_fft_variants", "fdas_frontend_plan", "fdas_frontend_exec",
-    "fdas_frontend_destroy",
+    "fdas_frontend_destroy", "fdas_convolve_batch_noalloc",
 )
 
 
@@ -102,6 +102,8 @@ def load():
     lib.fdas_convolve.restype = C.c_int
     lib.fdas_convolve_batch.argtypes = [C.c_void_p, P(Series), C.c_int, C.c_void_p]
     lib.fdas_convolve_batch.restype = C.c_int
+    lib.fdas_convolve_batch_noalloc.argtypes = [C.c_void_p, P(Series), C.c_int, C.c_void_p]
+    lib.fdas_convolve_batch_noalloc.restype = C.c_int
     lib.fdas_convolve_candidates.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_float,
                                              C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
     lib.fdas_convolve_candidates.restype = C.c_int
@@ -304,8 +306,7 @@ class Plan:
             _stream(spectrum.device)), "fdas_convolve_candidates")
         return rec, cnt
 
-    def convolve_batch(self, spectra, zmaxs, outs):
-        """Batched form: one launch over every series (see fdas_convolve_batch)."""
+    def _series(self, spectra, zmaxs, outs):
         import torch
         n = len(spectra)
         if not (n == len(zmaxs) == len(outs)) or n < 1:
@@ -321,8 +322,22 @@ class Plan:
                 _plane_ok(o, per * (int(round(span)) + 1), s.numel(), o.stride(0), s.device)
             arr[i] = Series(C.c_void_p(s.data_ptr()), s.numel(), float(z),
                             C.c_void_p(o.data_ptr()), o.stride(0))
-        dev = spectra[0].device
-        _check(self._lib.fdas_convolve_batch(self._h, arr, n, _stream(dev)), "fdas_convolve_batch")
+        return arr, n
+
+    def convolve_batch(self, spectra, zmaxs, outs):
+        """Batched form: one launch over every series (see fdas_convolve_batch)."""
+        arr, n = self._series(spectra, zmaxs, outs)
+        _check(self._lib.fdas_convolve_batch(self._h, arr, n, _stream(spectra[0].device)),
+               "fdas_convolve_batch")
+        return outs
+
+    def convolve_batch_noalloc(self, spectra, zmaxs, outs):
+        """The batched form without any device allocation (see
+        fdas_convolve_batch_noalloc): same results as convolve_batch."""
+        arr, n = self._series(spectra, zmaxs, outs)
+        _check(self._lib.fdas_convolve_batch_noalloc(self._h, arr, n,
+                                                     _stream(spectra[0].device)),
+               "fdas_convolve_batch_noalloc")
         return outs
 
     def close(self):

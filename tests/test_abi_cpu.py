@@ -189,3 +189,20 @@ def test_binding_rejects_output_buffers_that_do_not_fit():
                     (ok, 100)):                                 # stride differs from ld
         with pytest.raises((TypeError, ValueError)):
             fdas._plane_ok(bad, 5, 100, ld, dev)
+
+
+def test_noalloc_batch_rejects_on_host(lib):
+    """The allocation-free batch checks its arguments, and its series limit,
+    before anything touches the plan or the device (the plan pointer below is
+    never dereferenced)."""
+    assert lib.fdas_convolve_batch_noalloc(None, None, 0, None) == fdas.ERR_INVALID
+    n = 4097
+    arr = (fdas.Series * n)()
+    for i in range(n):
+        arr[i] = fdas.Series(C.c_void_p(0x1000), 10, 0.0, C.c_void_p(0x2000), 10)
+    fake = C.c_void_p(0x3000)
+    assert lib.fdas_convolve_batch_noalloc(fake, arr, n, None) == fdas.ERR_INVALID
+    assert "4096" in fdas.last_error()
+    arr[5] = fdas.Series(C.c_void_p(0x1004), 10, 0.0, C.c_void_p(0x2000), 10)  # misaligned
+    assert lib.fdas_convolve_batch_noalloc(fake, arr, 10, None) == fdas.ERR_INVALID
+    assert "series 5" in fdas.last_error()

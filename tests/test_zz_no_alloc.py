@@ -1,0 +1,72 @@
+"""The allocation-free batched entry point (fdas_convolve_batch_noalloc),
+through the C ABI: on two calls in a row, the second with a smaller batch,
+its planes equal those of fdas_convolve_batch bit for bit and match the FP64
+oracle within the form's bar; row padding is left untouched."""
+
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1711_10855_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+# (nbins, zmax, ld padding) per series
+FIRST = [(5000, 16.0, 0), (1, 8.0, 0), (191, 0.0, 3), (20000, 16.0, 7), (777, 4.0, 0),
+         (12345, 10.0, 0), (193, 16.0, 1)]
+SECOND = [(3000, 8.0, 0), (100, 16.0, 2)]
+# more series than one descriptor upload carries (64), then fewer
+MANY = [(50 + 37 * k, float(2 * (k % 9)), k % 3) for k in range(150)]
+
+
+def run(gpu, plan, specs, seed, noalloc):
+    import torch
+    spectra, zmaxs, outs = [], [], []
+    for k, (nbins, zmax, pad) in enumerate(specs):
+        a = synth.small_random_spectrum(nbins, seed=seed + k)
+        nz = int(round(zmax)) + 1   # dz = 2
+        spectra.append(a)
+        zmaxs.append(zmax)
+        outs.append(torch.full((nz, nbins + pad), -3.0, dtype=torch.float32, device="cuda"))
+    dev = [torch.from_numpy(a).cuda() for a in spectra]
+    views = [o[:, :a.size] for o, a in zip(outs, spectra)]
+    if noalloc:
+        plan.convolve_batch_noalloc(dev, zmaxs, views)
+    else:
+        plan.convolve_batch(dev, zmaxs, views)
+    torch.cuda.synchronize()
+    return spectra, zmaxs, [o.cpu().numpy() for o in outs]
+
+
+@pytest.mark.parametrize("prec,L,m,persistent", [("fp32", 256, 64, "0"), ("fp32", 1024, 128, "1"),
+                                                 ("fp16", 4096, 64, "0")])
+def test_noalloc_matches_the_batch_entry_point(gpu, monkeypatch, prec, L, m, persistent):
+    monkeypatch.setenv("FDAS_BATCH_PERSISTENT", persistent)
+    bar = 1e-4 if prec == "fp32" else 1e-3
+    with gpu.Plan(16.0, 2.0, m, L, prec) as p:
+        for call, (specs, seed) in enumerate(((FIRST, 300), (SECOND, 400), (MANY, 500),
+                                              (SECOND, 600))):
+            print(f"noalloc {prec} L={L} m={m} persistent={persistent} call {call} "
+                  f"nseries={len(specs)}", flush=True)
+            spectra, zmaxs, got = run(gpu, p, specs, seed, noalloc=True)
+            _, _, ref = run(gpu, p, specs, seed, noalloc=False)
+            for k, (a, z, g, r, (nbins, _, pad)) in enumerate(zip(spectra, zmaxs, got, ref, specs)):
+                assert np.array_equal(g, r), (call, k)
+                assert np.all(g[:, nbins:] == -3.0)
+                if call < 2 or k % 25 == 0:
+                    want = oracle.plane_direct(a, z, 2.0, m)
+                    assert np.max(np.abs(g[:, :nbins] - want)) <= bar * want.max(), (call, k)
+
+
+def test_noalloc_rejects_more_series_than_the_scratch_holds(gpu):
+    import torch
+    a = torch.from_numpy(synth.small_random_spectrum(64, seed=1)).cuda()
+    out = torch.empty((17, 64), dtype=torch.float32, device="cuda")
+    with gpu.Plan(16.0, 2.0, 64, 256) as p:
+        with pytest.raises(gpu.FdasError) as e:
+            p.convolve_batch_noalloc([a] * 4097, [16.0] * 4097, [out] * 4097)
+        assert e.value.status == gpu.ERR_INVALID
+        p.convolve_batch_noalloc([a], [16.0], [out])   # the plan is still usable
+        torch.cuda.synchronize()
