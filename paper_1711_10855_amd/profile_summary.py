@@ -99,10 +99,15 @@ def main():
                 avg_ns = float(r["AverageNs"])
         lines.append("")
 
-    sq = _one(os.path.join(d, "prof_sq", "*counter_collection.csv"))
-    if sq:
+    merged = {}
+    for sub in sorted(glob.glob(os.path.join(d, "prof_sq*"))):
+        sq = _one(os.path.join(sub, "*counter_collection.csv"))
+        if sq:
+            for k, c in _counters(sq, a.kernel_match).items():
+                merged.setdefault(k, {}).update(c)
+    if merged:
         lines += ["## SQ counters (per dispatch, mean)", ""]
-        for k, c in _counters(sq, a.kernel_match).items():
+        for k, c in merged.items():
             lines.append(f"`{k.split('(')[0][:110]}`")
             lines.append("")
             for name, v in sorted(c.items()):
@@ -112,6 +117,10 @@ def main():
             if "SQ_LDS_BANK_CONFLICT" in c and "SQ_LDS_IDX_ACTIVE" in c and c["SQ_LDS_IDX_ACTIVE"] > 0:
                 lines.append(f"- LDS bank-conflict cycles / LDS active cycles: "
                              f"{c['SQ_LDS_BANK_CONFLICT']/c['SQ_LDS_IDX_ACTIVE']:.3f}")
+            if "SQ_WAVE_CYCLES" in c and c["SQ_WAVE_CYCLES"] > 0:
+                for w in ("SQ_WAIT_ANY", "SQ_WAIT_INST_ANY", "SQ_ACTIVE_INST_ANY"):
+                    if w in c:
+                        lines.append(f"- {w} / SQ_WAVE_CYCLES: {c[w]/c['SQ_WAVE_CYCLES']:.3f}")
             lines.append("")
 
     def counter(sub, cname, match):
