@@ -89,6 +89,9 @@ def parse(argv=None):
     ap.add_argument("--candidates", type=float, default=None, metavar="THR",
                     help="single series: detection epilogue (points with power >= THR "
                          "listed) instead of writing the plane")
+    ap.add_argument("--peaks", type=float, default=None, metavar="THR",
+                    help="single series: detection epilogue with peak picking (3 x 3 local "
+                         "maxima at or above THR listed) instead of writing the plane")
     ap.add_argument("--nseries", type=int, default=None, help="batched: first N series only")
     ap.add_argument("--wave-gb", type=float, default=100.0,
                     help="batched: device memory budget for the planes of one wave")
@@ -97,7 +100,7 @@ def parse(argv=None):
     ap.add_argument("--no-check", action="store_true", help="skip the checks against the oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-bins", type=int, default=None,
-                    help="bins per sampled series the oracle timing covers (default 2^17 "
+                    help="bins per sampled series the oracle timing covers (default 2^18 "
                          "batched, 2^20 single series)")
     ap.add_argument("--cpu-workers", type=int, default=None,
                     help="oracle processes (default: usable cores, at most 16)")
@@ -361,8 +364,14 @@ def run_single(a_dev, zmax, dz, m, seg_len, prec, flags, args, keep_cols=0):
     info = plan.info
     nz, nbins = info.nz, a_dev.numel()
     stream = torch.cuda.current_stream(a_dev.device)
-    ncand = None
-    if args.candidates is None:
+    ncand = npeak = None
+    if args.peaks is not None:
+        buf = plan.peaks(a_dev, args.peaks, cand_capacity=1 << 20, peak_capacity=1 << 18)
+        ms, wall = _time(lambda: plan.peaks(a_dev, args.peaks, buf=buf), args.steps,
+                         args.warmup, args.warmup_s, stream)
+        ncand, npeak = (int(x) for x in buf[1].cpu()[:2])
+        check = None
+    elif args.candidates is None:
         out = torch.empty((nz, nbins), dtype=torch.float32, device=a_dev.device)
         ms, wall = _time(lambda: plan.convolve(a_dev, out=out), args.steps, args.warmup,
                          args.warmup_s, stream)
@@ -377,11 +386,16 @@ def run_single(a_dev, zmax, dz, m, seg_len, prec, flags, args, keep_cols=0):
     info = plan.get_info()  # templates per unit as the timed launches chose them
     plan.close()
     points = nz * nbins
-    bytes_launch = (4.0 * points if args.candidates is None else 16.0 * ncand) + 8.0 * nbins
+    if args.peaks is not None:    # input read, candidate list written, peaks written
+        bytes_launch = 8.0 * nbins + 16.0 * ncand + 16.0 * npeak
+    elif args.candidates is not None:
+        bytes_launch = 8.0 * nbins + 16.0 * ncand
+    else:
+        bytes_launch = 8.0 * nbins + 4.0 * points
     return {"points": points, "nz": nz, "nbins": nbins, "ms": ms, "wall": wall,
             "value": points / (ms * 1e-3), "bytes_launch": bytes_launch,
             "achieved": bytes_launch / (ms * 1e-3) / 1e9, "info": info, "ncand": ncand,
-            "check": check}
+            "npeak": npeak, "check": check}
 
 
 def traffic_from_profiles(kernel: str, workload: str):
@@ -432,7 +446,7 @@ def bench_batch(args, forms, line):
                                     args.sample_points) for i, sp in enumerate(specs)}
     n_dense = 8 if len({sp.zmax for sp in specs}) > 1 or len({sp.nbins for sp in specs}) > 1 else 4
     dense_ids = pick_series(specs, n_dense) if check or not args.no_cpu_baseline else []
-    dense_bins = min(args.cpu_sample_bins or (1 << 17), min(specs[i].nbins for i in dense_ids)) \
+    dense_bins = min(args.cpu_sample_bins or (1 << 18), min(specs[i].nbins for i in dense_ids)) \
         if dense_ids else 0
 
     results = {}
@@ -575,6 +589,10 @@ def bench_single(args, forms, line):
     if args.candidates is not None:
         line["config"]["epilogue"] = (f"threshold: points with power >= {args.candidates} "
                                       f"listed, no plane written ({r['ncand']} found)")
+    if args.peaks is not None:
+        line["config"]["epilogue"] = (f"threshold and peak picking: 3 x 3 local maxima with "
+                                      f"power >= {args.peaks} listed, no plane written "
+                                      f"({r['ncand']} candidates, {r['npeak']} peaks)")
     comp = {}
     for f, res in results.items():
         if f == head:
@@ -633,8 +651,8 @@ def main(argv=None):
     if bad or not forms:
         print(json.dumps({"error": f"unknown forms {bad}; known: {list(FORMS)}"}))
         sys.exit(2)
-    if args.candidates is not None and batched:
-        print(json.dumps({"error": "--candidates applies to single-series workloads"}))
+    if (args.candidates is not None or args.peaks is not None) and batched:
+        print(json.dumps({"error": "--candidates and --peaks apply to single-series workloads"}))
         sys.exit(2)
 
     import torch

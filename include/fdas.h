@@ -189,6 +189,34 @@ int fdas_convolve_candidates(fdas_plan_t plan, const void *spectrum, int64_t nbi
                              float threshold, fdas_candidate *cands, int64_t capacity,
                              unsigned long long *count, void *stream);
 
+/* The hot path with the whole detection epilogue: threshold, then peak
+ * picking (the candidate search that follows the plane, Section 3, which
+ * names it without defining it; the rule below is this library's reading).
+ * On the (z, r) grid -- plane row i and bin r, or with FDAS_FLAG_INTERBIN
+ * grid row i = plane row >> 1 and column 2 r + (row & 1), so neighbouring
+ * columns are half a bin apart -- a peak is a point with power >= threshold
+ * that outranks each of its (up to) eight neighbours: p outranks q when
+ * P_p > P_q, or P_p == P_q and p's (grid row, column) comes first. A
+ * plateau therefore has exactly one peak. No plane is written.
+ *   workspace      : device memory of fdas_peaks_workspace_bytes(cand_capacity)
+ *                    bytes or more, 16-byte aligned (candidate list and a
+ *                    hash table of grid cells).
+ *   cand_capacity  : candidates (points >= threshold) the workspace holds,
+ *                    0 .. FDAS_PEAKS_MAX_CANDIDATES. When more are found the
+ *                    peaks are not valid: compare counts[0] with it.
+ *   peaks          : device fdas_candidate [peak_capacity] (16-byte aligned),
+ *                    plane row and bin as in the power plane; the first
+ *                    min(counts[1], peak_capacity) entries, in no fixed order.
+ *   counts         : device uint64 [2]: candidates found, peaks found.
+ * Counters are cleared by a kernel on `stream`; kernels only, no allocation,
+ * no copy, no synchronisation.                                               */
+#define FDAS_PEAKS_MAX_CANDIDATES (1 << 30)
+size_t fdas_peaks_workspace_bytes(int64_t cand_capacity); /* 0 if out of range */
+int fdas_convolve_peaks(fdas_plan_t plan, const void *spectrum, int64_t nbins, float threshold,
+                        void *workspace, size_t workspace_bytes, int64_t cand_capacity,
+                        fdas_candidate *peaks, int64_t peak_capacity, unsigned long long *counts,
+                        void *stream);
+
 /* Batched hot path: one launch over every (series, template group, segment)
  * work item, largest series first (a flat grid of items; the FP32 kernels can
  * instead run persistent blocks taking items from a device counter when the

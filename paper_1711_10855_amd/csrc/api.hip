@@ -16,6 +16,7 @@
 #include "fft_batch.hpp"
 #include "frontend.hpp"
 #include "ols_variants.hpp"
+#include "peaks.hpp"
 #include "plan.hpp"
 
 namespace fdas {
@@ -266,6 +267,12 @@ int fdas_convolve(fdas_plan_t plan, const void *spectrum, int64_t nbins, float *
   if (ld < nbins) return set_error(FDAS_ERR_INVALID, "ld (%lld) < nbins (%lld)", (long long)ld, (long long)nbins);
   if ((reinterpret_cast<uintptr_t>(spectrum) & 7) || (reinterpret_cast<uintptr_t>(power) & 3))
     return set_error(FDAS_ERR_INVALID, "misaligned spectrum or power pointer");
+  {  // the plane is written while segments of the spectrum are still being read
+    const uintptr_t s0 = reinterpret_cast<uintptr_t>(spectrum), s1 = s0 + (uintptr_t)nbins * 8;
+    const uintptr_t p0 = reinterpret_cast<uintptr_t>(power);
+    const uintptr_t p1 = p0 + ((uintptr_t)(plan_rows(plan) - 1) * (uintptr_t)ld + (uintptr_t)nbins) * 4;
+    if (p0 < s1 && s0 < p1) return set_error(FDAS_ERR_INVALID, "power plane overlaps the spectrum");
+  }
   DeviceGuard guard(plan_device(plan));
   if (guard.err != hipSuccess) return hip_error(guard.err, "hipSetDevice");
   return plan_convolve(plan, spectrum, nbins, power, ld, (hipStream_t)stream);
@@ -287,6 +294,41 @@ int fdas_convolve_candidates(fdas_plan_t plan, const void *spectrum, int64_t nbi
   if (guard.err != hipSuccess) return hip_error(guard.err, "hipSetDevice");
   return plan_convolve_candidates(plan, spectrum, nbins, threshold, cands, capacity, count,
                                   (hipStream_t)stream);
+}
+
+size_t fdas_peaks_workspace_bytes(int64_t cand_capacity) {
+  if (cand_capacity < 0 || cand_capacity > FDAS_PEAKS_MAX_CANDIDATES) return 0;
+  return peaks_workspace_bytes(cand_capacity);
+}
+
+int fdas_convolve_peaks(fdas_plan_t plan, const void *spectrum, int64_t nbins, float threshold,
+                        void *workspace, size_t workspace_bytes, int64_t cand_capacity,
+                        fdas_candidate *peaks, int64_t peak_capacity, unsigned long long *counts,
+                        void *stream) {
+  if (!plan) return set_error(FDAS_ERR_INVALID, "null plan");
+  if (!spectrum || !counts || !workspace)
+    return set_error(FDAS_ERR_INVALID, "null spectrum, workspace or counts pointer");
+  if (nbins < 1 || nbins > ((int64_t)1 << 34))
+    return set_error(FDAS_ERR_INVALID, "nbins must be in [1, 2^34] (got %lld)", (long long)nbins);
+  if (cand_capacity < 0 || cand_capacity > FDAS_PEAKS_MAX_CANDIDATES)
+    return set_error(FDAS_ERR_INVALID, "candidate capacity %lld outside [0, %d]",
+                     (long long)cand_capacity, FDAS_PEAKS_MAX_CANDIDATES);
+  const size_t need = peaks_workspace_bytes(cand_capacity);
+  if (workspace_bytes < need)
+    return set_error(FDAS_ERR_INVALID, "workspace of %zu bytes; %zu needed for %lld candidates",
+                     workspace_bytes, need, (long long)cand_capacity);
+  if (peak_capacity < 0 || (peak_capacity > 0 && !peaks))
+    return set_error(FDAS_ERR_INVALID, "need peak capacity >= 0 and a list when it is > 0");
+  if (!std::isfinite(threshold)) return set_error(FDAS_ERR_INVALID, "threshold must be finite");
+  if ((reinterpret_cast<uintptr_t>(spectrum) & 7) || (reinterpret_cast<uintptr_t>(workspace) & 15) ||
+      (reinterpret_cast<uintptr_t>(peaks) & 15) || (reinterpret_cast<uintptr_t>(counts) & 7))
+    return set_error(FDAS_ERR_INVALID, "misaligned spectrum, workspace, peak list or counts");
+  if (plan_rows(plan) >= (1 << 27))
+    return set_error(FDAS_ERR_UNSUPPORTED, "more plane rows than the peak search indexes");
+  DeviceGuard guard(plan_device(plan));
+  if (guard.err != hipSuccess) return hip_error(guard.err, "hipSetDevice");
+  return plan_convolve_peaks(plan, spectrum, nbins, threshold, workspace, cand_capacity, peaks,
+                             peak_capacity, counts, (hipStream_t)stream);
 }
 
 // Argument checks shared by the two batched entry points (host only).

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "noalloc.hpp"
+#include "peaks.hpp"
 #include "plan.hpp"
 
 struct fdas_plan_s {
@@ -573,6 +574,28 @@ static int batch_args(fdas_plan_t pl, const SeriesDesc *d_desc, int nseries, int
   a->bank_log2 = 0;
   while ((1 << a->bank_log2) < pl->L) ++a->bank_log2;
   a->consts = pl->consts;
+  return FDAS_OK;
+}
+
+// Detection epilogue with peak picking: the candidate list goes to the head
+// of the workspace, the hash table of grid cells after it, and the peaks
+// kernels run after the correlation on the same stream.
+int plan_convolve_peaks(fdas_plan_t pl, const void *spec, int64_t nbins, float thr, void *work,
+                        int64_t cand_cap, void *peaks, int64_t peak_cap,
+                        unsigned long long *counts, hipStream_t s) {
+  hipError_t e = launch_peaks_reset(counts, s);
+  if (e != hipSuccess) return hip_error(e, "peak counter reset");
+  CandOut cd;
+  cd.list = static_cast<Cand *>(work);
+  cd.count = counts;
+  cd.cap = cand_cap;
+  cd.thr = thr;
+  const int st = plan_launch(pl, spec, nbins, nullptr, 0, cd, s);
+  if (st != FDAS_OK) return st;
+  void *table = static_cast<unsigned char *>(work) + (size_t)cand_cap * sizeof(Cand);
+  e = launch_peaks(cd.list, cand_cap, table, counts, (pl->p.flags & FDAS_FLAG_INTERBIN) ? 1 : 0,
+                   static_cast<Cand *>(peaks), peak_cap, s);
+  if (e != hipSuccess) return hip_error(e, "peak kernels");
   return FDAS_OK;
 }
 

@@ -28,6 +28,9 @@ int plan_convolve_batch_noalloc(fdas_plan_t plan, const fdas_series *series, int
                                 hipStream_t s);
 int plan_convolve_candidates(fdas_plan_t plan, const void *spec, int64_t nbins, float thr,
                              void *cands, int64_t cap, unsigned long long *count, hipStream_t s);
+int plan_convolve_peaks(fdas_plan_t plan, const void *spec, int64_t nbins, float thr, void *work,
+                        int64_t cand_cap, void *peaks, int64_t peak_cap,
+                        unsigned long long *counts, hipStream_t s);
 int destroy_plan(fdas_plan_t plan);
 
 }  // namespace fdas

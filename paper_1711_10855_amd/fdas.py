@@ -37,7 +37,8 @@ EXPORTS = (
     "fdas_destroy", "fdas_status_string", "fdas_last_error", "fdas_kernel_variants",
     "fdas_convolve_candidates", "fdas_fft_plan", "fdas_fft_get_info", "fdas_fft_exec",
     "fdas_fft_destroy", "fdas_fft_variants", "fdas_frontend_plan", "fdas_frontend_exec",
-    "fdas_frontend_destroy", "fdas_convolve_batch_noalloc",
+    "fdas_frontend_destroy", "fdas_convolve_batch_noalloc", "fdas_peaks_workspace_bytes",
+    "fdas_convolve_peaks",
 )
 
 
@@ -107,6 +108,12 @@ def load():
     lib.fdas_convolve_candidates.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_float,
                                              C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
     lib.fdas_convolve_candidates.restype = C.c_int
+    lib.fdas_peaks_workspace_bytes.argtypes = [C.c_int64]
+    lib.fdas_peaks_workspace_bytes.restype = C.c_size_t
+    lib.fdas_convolve_peaks.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_float,
+                                        C.c_void_p, C.c_size_t, C.c_int64, C.c_void_p,
+                                        C.c_int64, C.c_void_p, C.c_void_p]
+    lib.fdas_convolve_peaks.restype = C.c_int
     lib.fdas_destroy.argtypes = [C.c_void_p]
     lib.fdas_destroy.restype = C.c_int
     lib.fdas_status_string.argtypes = [C.c_int]
@@ -306,6 +313,43 @@ class Plan:
             _stream(spectrum.device)), "fdas_convolve_candidates")
         return rec, cnt
 
+    def peaks(self, spectrum, threshold, cand_capacity=1 << 16, peak_capacity=1 << 16, buf=None):
+        """Detection epilogue with peak picking (see fdas_convolve_peaks).
+
+        Returns (records, counts, workspace, cand_capacity): ``records`` a
+        device int64 tensor [peak_capacity, 2] of fdas_candidate entries
+        (decode with ``decode_peaks``), ``counts`` a device int64 tensor [2]
+        (candidates, peaks found), ``workspace`` the device buffer the search
+        used for ``cand_capacity`` candidates. ``buf`` may pass the tuple
+        back in to reuse it."""
+        import torch
+        if spectrum.dtype != torch.complex64 or not spectrum.is_cuda or spectrum.dim() != 1:
+            raise TypeError("spectrum must be a 1-D complex64 CUDA tensor")
+        spectrum = spectrum.contiguous()
+        dev = spectrum.device
+        if buf is None:
+            nbytes = self._lib.fdas_peaks_workspace_bytes(int(cand_capacity))
+            if nbytes == 0:
+                raise ValueError(f"candidate capacity {cand_capacity} out of range")
+            rec = torch.empty((peak_capacity, 2), dtype=torch.int64, device=dev)
+            cnt = torch.empty(2, dtype=torch.int64, device=dev)
+            work = torch.empty((nbytes + 15) // 16 * 2, dtype=torch.int64, device=dev)
+        else:
+            rec, cnt, work, cand_capacity = buf
+            if (rec.dtype != torch.int64 or rec.dim() != 2 or rec.shape[1] != 2
+                    or not rec.is_contiguous() or rec.device != dev or cnt.dtype != torch.int64
+                    or cnt.numel() < 2 or cnt.device != dev or work.device != dev
+                    or not work.is_contiguous()):
+                raise TypeError("buf must be (int64 [cap, 2], int64 [2], workspace, capacity) "
+                                "on the spectrum's device")
+            peak_capacity = rec.shape[0]
+        _check(self._lib.fdas_convolve_peaks(
+            self._h, C.c_void_p(spectrum.data_ptr()), spectrum.numel(), float(threshold),
+            C.c_void_p(work.data_ptr()), work.numel() * work.element_size(), int(cand_capacity),
+            C.c_void_p(rec.data_ptr()), int(peak_capacity), C.c_void_p(cnt.data_ptr()),
+            _stream(dev)), "fdas_convolve_peaks")
+        return rec, cnt, work, int(cand_capacity)
+
     def _series(self, spectra, zmaxs, outs):
         import torch
         n = len(spectra)
@@ -359,14 +403,23 @@ class Plan:
 
 
 def decode_candidates(rec, count):
-    """(row, r, power) numpy arrays from the tensors of Plan.candidates."""
+    """(row, r, power) numpy arrays from the tensors of Plan.candidates
+    (`count` the count tensor, or the count itself)."""
     import numpy as np
-    n = min(int(count.cpu()[0]), rec.shape[0])
+    n = min(count if isinstance(count, int) else int(count.cpu()[0]), rec.shape[0])
     raw = rec[:n].cpu().numpy()
     lo = raw[:, 0].astype(np.uint64)
     row = (lo & np.uint64(0xFFFFFFFF)).astype(np.uint32).view(np.int32)
     power = (lo >> np.uint64(32)).astype(np.uint32).view(np.float32)
     return row.astype(np.int64), raw[:, 1].copy(), power.astype(np.float32)
+
+
+def decode_peaks(rec, counts):
+    """(row, r, power) numpy arrays and the two counts (candidates, peaks)
+    from the tensors of Plan.peaks."""
+    n_cand, n_peak = (int(x) for x in counts.cpu()[:2])
+    row, r, power = decode_candidates(rec, n_peak)
+    return row, r, power, n_cand, n_peak
 
 
 def fft_variants(n=0):

@@ -206,3 +206,13 @@ def test_noalloc_batch_rejects_on_host(lib):
     arr[5] = fdas.Series(C.c_void_p(0x1004), 10, 0.0, C.c_void_p(0x2000), 10)  # misaligned
     assert lib.fdas_convolve_batch_noalloc(fake, arr, 10, None) == fdas.ERR_INVALID
     assert "series 5" in fdas.last_error()
+
+
+def test_peaks_workspace_and_host_checks(lib):
+    assert lib.fdas_peaks_workspace_bytes(-1) == 0
+    assert lib.fdas_peaks_workspace_bytes((1 << 30) + 1) == 0
+    assert lib.fdas_peaks_workspace_bytes(0) == 64 * 12            # the smallest table
+    assert lib.fdas_peaks_workspace_bytes(1000) == 1000 * 16 + 2048 * 12
+    assert lib.fdas_peaks_workspace_bytes(1024) == 1024 * 16 + 2048 * 12
+    assert lib.fdas_convolve_peaks(None, C.c_void_p(8), 10, 1.0, C.c_void_p(16), 1 << 20, 100,
+                                   C.c_void_p(16), 10, C.c_void_p(8), None) == fdas.ERR_INVALID
