@@ -93,7 +93,7 @@ def parse(argv=None):
                     help="single series: detection epilogue with peak picking (3 x 3 local "
                          "maxima at or above THR listed) instead of writing the plane")
     ap.add_argument("--nseries", type=int, default=None, help="batched: first N series only")
-    ap.add_argument("--wave-gb", type=float, default=100.0,
+    ap.add_argument("--wave-gb", type=float, default=150.0,
                     help="batched: device memory budget for the planes of one wave")
     ap.add_argument("--sample-points", type=int, default=2048,
                     help="batched: random plane points per series checked against the oracle")
@@ -197,23 +197,35 @@ def rel_error(got, ref) -> float:
     return float(np.max(np.abs(got - ref)) / np.max(ref))
 
 
-def sample_points(nbins: int, rows: int, zmax_s: float, dz: float, chirps, seed: int, k: int):
+def sample_points(nbins: int, rows: int, zmax_s: float, dz: float, chirps, seed: int, k: int,
+                  spectrum=None):
     """Plane points of one series checked against the oracle: the rows either
     side of every injected signal's drift and r0 - 2 .. r0 + 2 (where the
-    largest powers are), the first and last two bins on the first, last and
-    a middle row, and k points uniform over the plane. Returns (iz, r)."""
+    largest powers are), the rows next to z = 0 around the input's eight
+    strongest bins (the z = 0 row is |A_r|^2, so the plane's largest powers
+    of a series without a signal are near there), the first and last two
+    bins on the first, last and a middle row, and k points uniform over the
+    plane. Returns (iz, r)."""
     import numpy as np
     rng = np.random.default_rng(np.random.SeedSequence([171110855, 77, seed]))
     iz, r = [], []
-    for c in chirps:
-        f = (c.z0 + zmax_s) / dz
-        for row in {int(math.floor(f)), int(math.ceil(f))}:
+
+    def around(f, r0):
+        for row in range(int(math.floor(f)) - (1 if f == int(f) else 0), int(math.ceil(f)) + 1 +
+                         (1 if f == int(f) else 0)):
             if 0 <= row < rows:
                 for d in range(-2, 3):
-                    rr = int(round(c.r0)) + d
+                    rr = int(round(r0)) + d
                     if 0 <= rr < nbins:
                         iz.append(row)
                         r.append(rr)
+
+    for c in chirps:
+        around((c.z0 + zmax_s) / dz, c.r0)
+    if spectrum is not None:
+        p = np.abs(np.asarray(spectrum)) ** 2
+        for b in np.argpartition(p, -8)[-8:]:
+            around(zmax_s / dz, float(b))
     for row in {0, rows // 2, rows - 1}:
         for rr in {0, 1, nbins - 2, nbins - 1}:
             if 0 <= rr < nbins:
@@ -296,15 +308,19 @@ class Batch:
         # row starts on a cache-line boundary
         self.lds = [(sp.nbins + 63) // 64 * 64 for sp in self.specs]
         sizes = [r * ld * 4 for r, ld in zip(self.rows, self.lds)]
-        waves, cur, acc = [], [], 0
-        for i, b in enumerate(sizes):
-            if cur and acc + b > wave_bytes:
-                waves.append(cur)
-                cur, acc = [], 0
-            cur.append(i)
-            acc += b
-        if cur:
-            waves.append(cur)
+        # as few waves as the budget allows, filled evenly (a short last wave
+        # would leave most of the GPU idle): series i goes to the wave its
+        # midpoint falls in when the total is cut into nw equal parts
+        total, nw = sum(sizes), max(1, math.ceil(sum(sizes) / wave_bytes))
+        while True:
+            waves, acc = [[] for _ in range(nw)], 0
+            for i, b in enumerate(sizes):
+                waves[min(nw - 1, int((acc + b / 2) * nw / total))].append(i)
+                acc += b
+            waves = [wv for wv in waves if wv]
+            if max(sum(sizes[i] for i in wv) for wv in waves) <= wave_bytes or nw >= len(sizes):
+                break
+            nw += 1
         self.waves = waves
         self.buf = torch.empty(max(sum(sizes[i] for i in wv) for wv in waves) // 4,
                                dtype=torch.float32, device=dev)
@@ -443,7 +459,8 @@ def bench_batch(args, forms, line):
     samples = None
     if check:
         samples = {i: sample_points(sp.nbins, b.rows[i] // b.per, sp.zmax, w.dz, sp.chirps, i,
-                                    args.sample_points) for i, sp in enumerate(specs)}
+                                    args.sample_points, b.spectra[i])
+                   for i, sp in enumerate(specs)}
     n_dense = 8 if len({sp.zmax for sp in specs}) > 1 or len({sp.nbins for sp in specs}) > 1 else 4
     dense_ids = pick_series(specs, n_dense) if check or not args.no_cpu_baseline else []
     dense_bins = min(args.cpu_sample_bins or (1 << 18), min(specs[i].nbins for i in dense_ids)) \
@@ -500,9 +517,10 @@ def bench_batch(args, forms, line):
                     "worst_series": worst,
                     "per_series": [float(f"{e:.3g}") for e in per],
                     "dense": {str(k): float(f"{v:.3g}") for k, v in dense.items()},
-                    "sample": f"per series: {args.sample_points} uniform plane points plus "
-                              "r0 +- 2 on the rows either side of each injected signal and "
-                              "both edges, max P_ref over those points; dense: every row x "
+                    "sample": f"per series: {args.sample_points} uniform plane points, "
+                              "r0 +- 2 on the rows either side of each injected signal, "
+                              "the input's 8 strongest bins +- 2 on the rows next to z = 0, "
+                              "both edges; max P_ref over those points; dense: every row x "
                               f"the first {ncol} bins of the series listed"}
         pool.close()
 

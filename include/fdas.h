@@ -217,13 +217,15 @@ int fdas_convolve_peaks(fdas_plan_t plan, const void *spectrum, int64_t nbins, f
                         fdas_candidate *peaks, int64_t peak_capacity, unsigned long long *counts,
                         void *stream);
 
-/* Batched hot path: one launch over every (series, template group, segment)
- * work item, largest series first (a flat grid of items; the FP32 kernels can
- * instead run persistent blocks taking items from a device counter when the
- * environment sets FDAS_BATCH_PERSISTENT=1). Each series uses the central
- * rows of the plan's bank. The launch is captured once into a HIP graph per
- * distinct batch shape and replayed. `series` is host memory with
- * nseries >= 1 entries.                                                      */
+/* Batched hot path: one persistent launch over every (series, template group,
+ * segment) work item, largest series first: as many blocks as the GPU holds
+ * at once take items from a device counter (reset by a kernel in the same
+ * graph) until none is left. FDAS_BATCH_PERSISTENT=0 in the environment
+ * selects a flat grid of one block per item instead. Each series uses the
+ * central rows of the plan's bank; a batch that fills the GPU many times over
+ * gives each (series, segment) one work item for all its templates. The
+ * launch is captured once into a HIP graph per distinct batch shape and
+ * replayed. `series` is host memory with nseries >= 1 entries.               */
 int fdas_convolve_batch(fdas_plan_t plan, const fdas_series *series,
                         int nseries, void *stream);
 

@@ -221,8 +221,6 @@ __global__ void __launch_bounds__(Gm::T *G) __attribute__((amdgpu_waves_per_eu(W
   __shared__ c32 lds[NB][G][Gm::LP];
   __shared__ long long s_item[2];
   const int tid = threadIdx.x;
-  const int sg = tid / T;
-  const int t = tid % T;
   int par = 0;
   for (;;) {
     if (tid == 0) s_item[par] = (long long)atomicAdd(counter, 1ULL);
@@ -242,6 +240,13 @@ __global__ void __launch_bounds__(Gm::T *G) __attribute__((amdgpu_waves_per_eu(W
     const int nsb = (d.nseg + G - 1) / G;
     const int zg = (int)(local / nsb);
     const int sb = (int)(local % nsb);
+    // The thread index passes through an empty asm statement on every item, so
+    // that nothing computed from it is hoisted out of this loop (held across
+    // it, one unit's addresses spilled: the loop measured twice as slow).
+    int tid_i;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(tid_i) : "v"(tid));
+    const int sg = tid_i / T;
+    const int t = tid_i % T;
     const int s = sb * G + sg;
     const int z0 = d.row_off + zg * d.zpb;
     const int z1 = min(d.row_off + d.nz, z0 + d.zpb);
@@ -253,9 +258,9 @@ __global__ void __launch_bounds__(Gm::T *G) __attribute__((amdgpu_waves_per_eu(W
 }
 
 // Batch as one flat launch: block b takes work item b (same numbering), so
-// the hardware dispatcher hands out items in order as blocks retire. This is
-// the default batch form: on the register-heavy FP32 kernels the persistent
-// loop above measured up to twice as slow per item as this launch.
+// the hardware dispatcher hands out items in order as blocks retire
+// (FDAS_BATCH_PERSISTENT=0; the persistent loop above is the default, 1%
+// faster on the batched workloads).
 template <class Gm, int G, bool TWREG, bool PF, int WPE>
 __global__ void __launch_bounds__(Gm::T *G) __attribute__((amdgpu_waves_per_eu(WPE)))
     ols_fp32_items_kernel(const SeriesDesc *__restrict__ desc, int nseries,
@@ -296,7 +301,7 @@ hipError_t launch_reset_counter(unsigned long long *counter, hipStream_t s) {
 
 static bool batch_persistent() {
   const char *e = std::getenv("FDAS_BATCH_PERSISTENT");
-  return e && *e == '1';
+  return !(e && *e == '0');  // the flat item grid with FDAS_BATCH_PERSISTENT=0
 }
 
 // ---- variant registry ------------------------------------------------------

@@ -38,6 +38,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstdlib>
 #include <type_traits>
 
 #include "fft_radix.hpp"
@@ -222,14 +223,14 @@ __device__ __forceinline__ void load_mixed_consts(MixedConsts<H, NW, SPLIT> &K,
 
 // One work unit of the mixed kernel: segment s, bank rows [z0, z1), plane
 // rows iz - row_base. Every thread of the block calls it (barriers inside).
-template <class H, bool PF, bool NT, int NW, bool SPLIT, bool CAND>
+template <class H, int PF, bool NT, int NW, bool SPLIT, bool CAND>
 __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ consts_,
                                            const c32 *__restrict__ spec_, int64_t nbins,
                                            const H *__restrict__ bank_, const c32 *__restrict__ tw_,
                                            float *__restrict__ power_, int64_t ld, int s,
                                            bool active, int U, int half, int z0, int z1,
                                            int row_base, int bank_log2, unsigned char *smem,
-                                           float *s_max, const CandOut &cd) {
+                                           float *s_max, const CandOut &cd, int t_in = -1) {
   typedef typename Vec<H>::v8 v8;
   constexpr int L = 4096;
   constexpr int TPW = 16 / NW;
@@ -245,7 +246,8 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
   H *Xp = Eb;  // X passes through Eb once; first overwritten by stage 1' of the first template
   c32 *Xf = reinterpret_cast<c32 *>(Eb);  // (SPLIT) the same, in FP32
   float *stg = reinterpret_cast<float *>(smem + mix_stage_bytes<SPLIT>());
-  const int t = threadIdx.x;
+  // (the persistent form passes the thread index in; see there)
+  const int t = t_in < 0 ? (int)threadIdx.x : t_in;
   const int lane = t & 63, w = t >> 6;
   const int g = lane >> 4, c = lane & 15, h = g & 1;
   const int64_t seg0 = (int64_t)s * U - half;
@@ -417,10 +419,18 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
 
   // Per template: product + stage 2' | barrier | stage 1', stores of the
   // previous template's staged powers | barrier | stage 0' into the staging
-  // buffer. With PF the next bank row is loaded after those stores, so the
-  // wait for it (vector loads and stores share one counter) comes a full
-  // phase after both were issued.
+  // buffer. Vector loads and stores share one counter, and with both kinds
+  // outstanding a wait for a load also waits for every store issued before
+  // it. PF == 1: the next bank row is loaded after the stores, so the wait
+  // for it (at the next product) comes a full phase after both were issued.
+  // PF == 2: the next bank row is loaded as soon as the product has read the
+  // current one, and everything outstanding is waited for explicitly at the
+  // start of the following phase, before the stores are issued: loads get one
+  // phase and the stores of the previous template two.
   if (PF && z0 < z1) load_bank(z0);
+  // (PF == 2: nothing may be outstanding on entry, or the loads of the
+  // preheader would make every later wait a full one)
+  if constexpr (PF == 2) __builtin_amdgcn_s_waitcnt(0x0F70);
   for (int iz = z0; iz < z1; ++iz) {
     if (!PF) load_bank(iz);
     // ---- product + stage 2' (tiles k0 = TPW w + j; rows k1 = c; chunk h) ----
@@ -449,7 +459,10 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
       // lane holds rows k1 = 4g + i, column n2 = c
       store_stage<H, SPLIT>(Ea, 16 * c + k0, g, dr, di);  // stage 1' butterfly (k0, n2 = c)
     }
+    if (PF == 2 && iz + 1 < z1) load_bank(iz + 1);
     __syncthreads();
+    // vmcnt(0), expcnt and lgkmcnt at their maxima (no wait on them)
+    if constexpr (PF == 2) __builtin_amdgcn_s_waitcnt(0x0F70);
     // ---- stage 1' (tiles n2 = TPW w + j; rows k0 = c) -------------------------
 #pragma unroll
     for (int j = 0; j < TPW; ++j) {
@@ -462,7 +475,7 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
       store_stage<H, SPLIT>(Eb, 16 * c + n2, g, dr, di);  // stage 0' butterfly (n1 = c, n2)
     }
     if (iz > z0) store_staged(iz - 1);
-    if (PF && iz + 1 < z1) load_bank(iz + 1);
+    if (PF == 1 && iz + 1 < z1) load_bank(iz + 1);
     __syncthreads();
     // ---- stage 0' (tiles n1 = TPW w + j; rows n2 = c) + |.|^2 -> staging ----
 #pragma unroll
@@ -484,7 +497,7 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
   }
 }
 
-template <class H, bool PF, bool NT, int NW, int OCC, bool SPLIT, bool CAND>
+template <class H, int PF, bool NT, int NW, int OCC, bool SPLIT, bool CAND>
 __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(OCC, OCC)))
     ols_mixed4096_kernel(const c32 *__restrict__ spec, int64_t nbins, const H *__restrict__ bank,
                          const c32 *__restrict__ tw, const unsigned char *__restrict__ consts,
@@ -503,9 +516,9 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(OC
 // Batched form as one flat launch: block b takes work item b (items are
 // numbered largest series first, template-group major), so the hardware
 // dispatcher hands out items in that order as blocks retire. Same body as
-// the single-series kernel; used because the persistent loop around this
-// body does not fit the register budget.
-template <class H, bool PF, bool NT, int NW, int OCC, bool SPLIT>
+// the single-series kernel (FDAS_BATCH_PERSISTENT=0; the persistent form
+// below is the default).
+template <class H, int PF, bool NT, int NW, int OCC, bool SPLIT>
 __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(OCC, OCC)))
     ols_mixed4096_items_kernel(const SeriesDesc *__restrict__ desc, int nseries,
                                const H *__restrict__ bank, const c32 *__restrict__ tw,
@@ -532,7 +545,7 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(OC
                             none);
 }
 
-template <class H, bool PF, bool NT, int NW, int OCC, bool SPLIT>
+template <class H, int PF, bool NT, int NW, int OCC, bool SPLIT>
 static hipError_t launch_mixed4096(const OlsArgs &a, hipStream_t st) {
   const int nsb = a.nseg;
   const int nzg = (a.nz + a.zpb - 1) / a.zpb;
@@ -552,8 +565,67 @@ static hipError_t launch_mixed4096(const OlsArgs &a, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <class H, bool PF, bool NT, int NW, int OCC, bool SPLIT>
+// Persistent batched form: a grid sized to the resident blocks, each block
+// taking work items from a device counter (reset by a kernel launched just
+// before) until none is left. The same body as the flat form.
+template <class H, int PF, bool NT, int NW, int OCC, bool SPLIT>
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(OCC, OCC)))
+    ols_mixed4096_persistent_kernel(const SeriesDesc *__restrict__ desc, int nseries,
+                                    long long total, unsigned long long *counter,
+                                    const H *__restrict__ bank, const c32 *__restrict__ tw,
+                                    const unsigned char *__restrict__ consts, int U, int half,
+                                    int bank_log2) {
+  __shared__ __attribute__((aligned(16))) unsigned char smem[mix_smem<SPLIT>()];
+  __shared__ float s_max[NW];
+  __shared__ long long s_item[2];
+  int par = 0;
+  for (;;) {
+    if (threadIdx.x == 0) s_item[par] = (long long)atomicAdd(counter, 1ULL);
+    __syncthreads();
+    const long long item = s_item[par];
+    par ^= 1;
+    if (item >= total) break;  // every wave of the block sees the same item
+    int lo = 0, hi = nseries - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (desc[mid].item_begin <= item) lo = mid;
+      else hi = mid - 1;
+    }
+    const SeriesDesc d = desc[lo];
+    const long long local = item - d.item_begin;
+    const int zg = (int)(local / d.nseg);
+    const int sb = (int)(local % d.nseg);
+    const int z0 = d.row_off + zg * d.zpb;
+    const int z1 = min(d.row_off + d.nz, z0 + d.zpb);
+    const CandOut none{};
+    // The thread index passes through an empty asm statement on every item, so
+    // that nothing computed from it is hoisted out of this loop (held across
+    // it, the addresses of one unit would not fit the register budget).
+    int t;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(t) : "v"((int)threadIdx.x));
+    mixed_unit<H, PF, NT, NW, SPLIT, false>(consts, static_cast<const c32 *>(d.spec), d.nbins,
+                                            bank, tw, d.power, d.ld, sb, true, U, half, z0, z1,
+                                            d.row_off, bank_log2, smem, s_max, none, t);
+  }
+}
+
+static bool mixed_batch_persistent() {
+  const char *e = std::getenv("FDAS_BATCH_PERSISTENT");
+  return !(e && *e == '0');  // the flat item grid with FDAS_BATCH_PERSISTENT=0
+}
+
+template <class H, int PF, bool NT, int NW, int OCC, bool SPLIT>
 static hipError_t launch_mixed4096_batch(const BatchArgs &a, hipStream_t st) {
+  if (mixed_batch_persistent()) {
+    hipError_t e = launch_reset_counter(a.counter, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((ols_mixed4096_persistent_kernel<H, PF, NT, NW, OCC, SPLIT>),
+                       dim3((unsigned)a.grid), dim3(64 * NW), 0, st, a.desc, a.nseries,
+                       (long long)a.total, a.counter, static_cast<const H *>(a.bank),
+                       static_cast<const c32 *>(a.tw), static_cast<const unsigned char *>(a.consts),
+                       a.U, a.half, a.bank_log2);
+    return hipGetLastError();
+  }
   if (a.total > (int64_t)0xffffffffLL) return hipErrorInvalidValue;
   hipLaunchKernelGGL((ols_mixed4096_items_kernel<H, PF, NT, NW, OCC, SPLIT>), dim3((unsigned)a.total),
                      dim3(64 * NW), 0, st, a.desc, a.nseries, static_cast<const H *>(a.bank),
@@ -562,12 +634,18 @@ static hipError_t launch_mixed4096_batch(const BatchArgs &a, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <class H, bool PF, bool NT, int NW, int OCC, bool SPLIT>
+template <class H, int PF, bool NT, int NW, int OCC, bool SPLIT>
 static int mixed_batch_blocks_per_cu() {
-  return 1;  // flat launch: the grid is the item count
+  if (!mixed_batch_persistent()) return 1;  // flat launch: the grid is the item count
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &nb, reinterpret_cast<const void *>(&ols_mixed4096_persistent_kernel<H, PF, NT, NW, OCC, SPLIT>),
+          64 * NW, 0) != hipSuccess)
+    return 1;
+  return nb;
 }
 
-template <class H, bool PF, bool NT, int NW, int OCC, bool SPLIT>
+template <class H, int PF, bool NT, int NW, int OCC, bool SPLIT>
 static int mixed_grid_blocks_per_cu() {
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
@@ -577,7 +655,7 @@ static int mixed_grid_blocks_per_cu() {
   return nb;
 }
 
-template <class H, bool PF, bool NT, int NW, int OCC, bool SPLIT>
+template <class H, int PF, bool NT, int NW, int OCC, bool SPLIT>
 static OlsVariant make_mixed(const char *name, int precision) {
   OlsVariant v{};
   v.name = name;
@@ -606,14 +684,18 @@ static OlsVariant make_mixed(const char *name, int precision) {
 }
 
 static const OlsVariant kMixedVariants[] = {
+    make_mixed<_Float16, 2, true, 16, 8, false>("fp16_L4096_mfma_w16_pfw", 1),
     make_mixed<_Float16, true, true, 16, 8, false>("fp16_L4096_mfma_w16_pf", 1),
     make_mixed<_Float16, false, true, 16, 8, false>("fp16_L4096_mfma_w16", 1),
     make_mixed<_Float16, true, true, 8, 4, false>("fp16_L4096_mfma_w8_pf", 1),
     make_mixed<_Float16, false, true, 8, 4, false>("fp16_L4096_mfma_w8", 1),
     make_mixed<_Float16, true, false, 16, 8, false>("fp16_L4096_mfma_w16_pf_ts", 1),
+    make_mixed<__bf16, 2, true, 16, 8, false>("bf16_L4096_mfma_w16_pfw", 2),
     make_mixed<__bf16, true, true, 16, 8, false>("bf16_L4096_mfma_w16_pf", 2),
     make_mixed<__bf16, true, true, 8, 4, false>("bf16_L4096_mfma_w8_pf", 2),
     // hi + lo split products (FDAS_FLAG_SPLIT)
+    make_mixed<_Float16, 2, true, 16, 4, true>("fp16_L4096_mfma_split_w16_pfw", 1),
+    make_mixed<__bf16, 2, true, 16, 4, true>("bf16_L4096_mfma_split_w16_pfw", 2),
     make_mixed<_Float16, false, true, 16, 4, true>("fp16_L4096_mfma_split_w16", 1),
     make_mixed<_Float16, true, true, 16, 4, true>("fp16_L4096_mfma_split_w16_pf", 1),
     make_mixed<__bf16, false, true, 16, 4, true>("bf16_L4096_mfma_split_w16", 2),

@@ -519,7 +519,7 @@ int plan_convolve_candidates(fdas_plan_t pl, const void *spec, int64_t nbins, fl
 
 // One series of a batch: check its zmax against the plan's z grid and fill
 // its descriptor (all but the first work item); `cost` orders the series.
-static int series_desc(fdas_plan_t pl, const fdas_series &x, int i, SeriesDesc *d,
+static int series_desc(fdas_plan_t pl, const fdas_series &x, int i, int zpb, SeriesDesc *d,
                        double *cost) {
   const double dz = pl->p.dz;
   if (!std::isfinite(x.zmax) || x.zmax < 0.0 || x.zmax > pl->p.zmax * (1.0 + 1e-12) + 1e-12)
@@ -539,11 +539,30 @@ static int series_desc(fdas_plan_t pl, const fdas_series &x, int i, SeriesDesc *
   d->nseg = (int)nseg;
   d->nz = per * ((int)std::nearbyint(span) + 1);
   d->row_off = per * (int)std::nearbyint(off);
-  // near-equal template groups of at most the plan's templates per unit
-  const int ng = (d->nz + pl->zpb - 1) / pl->zpb;
+  // near-equal template groups of at most zpb templates
+  const int ng = (d->nz + zpb - 1) / zpb;
   d->zpb = (d->nz + ng - 1) / ng;
   *cost = (double)d->nz * (double)x.nbins;
   return FDAS_OK;
+}
+
+// Templates per work item of a batch whose series have `nsb` segment groups
+// in all. A batch that fills the grid many times over has no tail to
+// balance, and one unit per (series, segment) pays the forward transform
+// once per segment: 3-4% faster than units of 40 (FP32) or 72 (matrix cores)
+// on 118 series of 2^21 bins at 201 templates. Smaller batches keep the
+// plan's unit size, as does a size fixed by FDAS_ZPB or the autotuner.
+static int batch_zpb(fdas_plan_t pl, int64_t nsb) {
+  if (pl->zpb_forced) return pl->zpb;
+  if (!pl->slots) {
+    int cus = 0;
+    const int per = pl->var->grid_blocks_per_cu ? pl->var->grid_blocks_per_cu() : 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, pl->device) != hipSuccess ||
+        per <= 0 || cus <= 0)
+      return pl->zpb;
+    pl->slots = cus * per;
+  }
+  return nsb >= 8 * (int64_t)pl->slots ? INT_MAX / 2 : pl->zpb;
 }
 
 static int64_t series_items(const SeriesDesc &d, int G) {
@@ -608,9 +627,16 @@ int plan_convolve_batch(fdas_plan_t pl, const fdas_series *series, int nseries, 
   const int G = pl->var->G;
   std::vector<SeriesDesc> desc(nseries);
   std::vector<double> cost(nseries);
+  int64_t nsb = 0;
   for (int i = 0; i < nseries; ++i) {
-    const int st = series_desc(pl, series[i], i, &desc[i], &cost[i]);
+    const int st = series_desc(pl, series[i], i, pl->zpb, &desc[i], &cost[i]);
     if (st != FDAS_OK) return st;
+    nsb += (desc[i].nseg + G - 1) / G;
+  }
+  const int zpb = batch_zpb(pl, nsb);
+  for (int i = 0; i < nseries; ++i) {
+    const int ng = (desc[i].nz + zpb - 1) / zpb;
+    desc[i].zpb = (desc[i].nz + ng - 1) / ng;
   }
   std::vector<int> order(nseries);
   std::iota(order.begin(), order.end(), 0);
@@ -719,12 +745,15 @@ int plan_convolve_batch_noalloc(fdas_plan_t pl, const fdas_series *series, int n
   const int G = pl->var->G;
   double cost[kNoAllocMaxSeries];
   int order[kNoAllocMaxSeries];
+  int64_t nsb = 0;
   for (int i = 0; i < nseries; ++i) {
     SeriesDesc d;
-    const int st = series_desc(pl, series[i], i, &d, &cost[i]);
+    const int st = series_desc(pl, series[i], i, pl->zpb, &d, &cost[i]);
     if (st != FDAS_OK) return st;
     order[i] = i;
+    nsb += (d.nseg + G - 1) / G;
   }
+  const int zpb = batch_zpb(pl, nsb);
   // largest first, ties in input order (the order the graph path uses)
   std::sort(order, order + nseries,
             [&](int a, int b) { return cost[a] > cost[b] || (cost[a] == cost[b] && a < b); });
@@ -741,7 +770,7 @@ int plan_convolve_batch_noalloc(fdas_plan_t pl, const fdas_series *series, int n
   for (int k = 0; k < nseries; ++k) {
     SeriesDesc &d = chunk.d[chunk.n];
     double c = 0.0;
-    (void)series_desc(pl, series[order[k]], order[k], &d, &c);
+    (void)series_desc(pl, series[order[k]], order[k], zpb, &d, &c);
     d.item_begin = total;
     total += series_items(d, G);
     if (++chunk.n == kDescChunk || k == nseries - 1) {

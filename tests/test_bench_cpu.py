@@ -84,6 +84,13 @@ def test_sample_points_cover_signals_and_edges():
     assert iz.min() >= 0 and iz.max() < 33 and r.min() >= 0 and r.max() < 5000
     again = bench.sample_points(5000, 33, 32.0, 2.0, chirps, 3, 100)
     assert np.array_equal(again[0], iz) and np.array_equal(again[1], r)
+    # with the spectrum: its strongest bins on the rows next to z = 0 (row 16)
+    a = np.ones(5000, dtype=np.complex64)
+    a[[10, 4999]] = 5.0
+    iz, r = bench.sample_points(5000, 33, 32.0, 2.0, [], 3, 0, a)
+    pts = set(zip(iz.tolist(), r.tolist()))
+    assert {(15, 8), (16, 10), (17, 12), (16, 4997), (17, 4999)} <= pts
+    assert iz.min() >= 0 and iz.max() < 33 and r.max() < 5000
 
 
 def test_pick_series():

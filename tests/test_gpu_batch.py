@@ -1,6 +1,6 @@
 """Batched path (one graph-captured launch over many series of uneven length
-and per-series zmax; flat work-item grid by default, persistent work-queue
-loop with FDAS_BATCH_PERSISTENT=1) against the FP64 oracle, through the C ABI."""
+and per-series zmax; persistent work-queue loop by default, flat work-item
+grid with FDAS_BATCH_PERSISTENT=0) against the FP64 oracle, through the C ABI."""
 
 import os
 

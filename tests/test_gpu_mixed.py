@@ -92,8 +92,11 @@ def test_mixed_workload_sampled_points(gpu):
     assert err <= TOL_MIXED
 
 
-def test_mixed_batch_matches_oracle(gpu):
+@pytest.mark.parametrize("persistent", ["0", "1"])
+def test_mixed_batch_matches_oracle(gpu, monkeypatch, persistent):
+    """Flat item grid, and persistent blocks taking items from a counter."""
     import torch
+    monkeypatch.setenv("FDAS_BATCH_PERSISTENT", persistent)
     specs = [(9000, 16.0), (1, 4.0), (4100, 0.0), (20000, 10.0), (3841, 16.0)]
     spectra = [synth.small_random_spectrum(n, seed=300 + k) for k, (n, _) in enumerate(specs)]
     outs = [torch.full((int(round(z)) + 1, n + 2), -5.0, dtype=torch.float32, device="cuda")
@@ -104,7 +107,7 @@ def test_mixed_batch_matches_oracle(gpu):
     for (n, z), a, o in zip(specs, spectra, res):
         ref = oracle.plane_direct(a, z, 2.0, 256)
         err = rel_err(o[:, :n], ref)
-        print(f"fp16 batch nbins={n} zmax={z}: {err:.3e}")
+        print(f"fp16 batch nbins={n} zmax={z} persistent={persistent}: {err:.3e}")
         assert err <= TOL_MIXED
         assert np.all(o[:, n:] == -5.0)
 
