@@ -143,20 +143,30 @@ __device__ __forceinline__ void ols_unit(const c32 *__restrict__ spec_, int64_t 
 
     // outputs: slot j*R0 + n holds index n * S0 + t + j T of the segment
     if constexpr (CAND) {
-      // detection epilogue: every lane takes part in each offer (one atomic
-      // per wave that has a hit)
+      // detection epilogue: the powers first (the transform's registers are
+      // then free), one ballot to skip a wave with no hit at all (the common
+      // case), else every lane takes part in each offer (one atomic per wave
+      // that has a hit)
       constexpr int S0 = Gm::S(0), R0 = Gm::R[0];
+      float pw[E];
+      bool any = false;
 #pragma unroll
-      for (int j = 0; j < Gm::B(0); ++j)
+      for (int e = 0; e < E; ++e) {
+        pw[e] = __builtin_fmaf(y[e].x, y[e].x, y[e].y * y[e].y);
+        any |= pw[e] >= cd.thr;
+      }
+      if (__builtin_amdgcn_ballot_w64(active && any) != 0ull) {
 #pragma unroll
-        for (int n = 0; n < R0; ++n) {
-          const int o = n * S0 + t + j * T;
-          const int64_t r = (int64_t)s * U + o - half;
-          const c32 v = y[j * R0 + n];
-          const float pw = __builtin_fmaf(v.x, v.x, v.y * v.y);
-          const bool hit = active && o >= half && o < half + U && r < nbins && pw >= cd.thr;
-          cand_offer(cd, hit, iz - row_base, r, pw);
-        }
+        for (int j = 0; j < Gm::B(0); ++j)
+#pragma unroll
+          for (int n = 0; n < R0; ++n) {
+            const int o = n * S0 + t + j * T;
+            const int64_t r = (int64_t)s * U + o - half;
+            const float p = pw[j * R0 + n];
+            const bool hit = active && o >= half && o < half + U && r < nbins && p >= cd.thr;
+            cand_offer(cd, hit, iz - row_base, r, p);
+          }
+      }
     } else if (active) {
       constexpr int S0 = Gm::S(0), R0 = Gm::R[0];
       const auto prow = power + (int64_t)(iz - row_base) * ld;

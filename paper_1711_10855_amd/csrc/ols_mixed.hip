@@ -384,16 +384,25 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
   const bool vec_ok = half % 4 == 0 && ((int64_t)s * U - half) % 4 == 0 &&
                       (int64_t)(s + 1) * U <= nbins && ld % 4 == 0 &&
                       (reinterpret_cast<uintptr_t>(power_) & 15) == 0;
-  auto store_staged = [&](int izr) {
+  // The staged powers of the wave's TPW output blocks (one 16-byte LDS read
+  // each), then their stores (or candidate offers).
+  auto read_staged = [&](f4 *v) {
+#pragma unroll
+    for (int q = 0; q < TPW; ++q)
+      v[q] = *reinterpret_cast<const f4 *>(stg + 260 * (TPW * w + q) + 4 * lane);
+  };
+  auto write_staged = [&](int izr, const f4 *vv) {
     if (!CAND && !active) return;
     const auto prow = power + (int64_t)(izr - row_base) * ld;
 #pragma unroll
     for (int q = 0; q < TPW; ++q) {
       const int blk = TPW * w + q;  // 256-output block of the segment
       const int o0 = 256 * blk + 4 * lane;
-      const f4 v = *reinterpret_cast<const f4 *>(stg + 260 * blk + 4 * lane);
+      const f4 v = vv[q];
       const int64_t r0 = (int64_t)s * U + o0 - half;
       if constexpr (CAND) {  // detection epilogue instead of the plane (all lanes offer)
+        const bool any = v[0] >= cd.thr || v[1] >= cd.thr || v[2] >= cd.thr || v[3] >= cd.thr;
+        if (__builtin_amdgcn_ballot_w64(active && any) == 0ull) continue;  // no hit in the wave
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int o = o0 + i;
@@ -416,24 +425,14 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
       }
     }
   };
+  auto store_staged = [&](int izr) {
+    f4 v[TPW];
+    read_staged(v);
+    write_staged(izr, v);
+  };
 
-  // Per template: product + stage 2' | barrier | stage 1', stores of the
-  // previous template's staged powers | barrier | stage 0' into the staging
-  // buffer. Vector loads and stores share one counter, and with both kinds
-  // outstanding a wait for a load also waits for every store issued before
-  // it. PF == 1: the next bank row is loaded after the stores, so the wait
-  // for it (at the next product) comes a full phase after both were issued.
-  // PF == 2: the next bank row is loaded as soon as the product has read the
-  // current one, and everything outstanding is waited for explicitly at the
-  // start of the following phase, before the stores are issued: loads get one
-  // phase and the stores of the previous template two.
-  if (PF && z0 < z1) load_bank(z0);
-  // (PF == 2: nothing may be outstanding on entry, or the loads of the
-  // preheader would make every later wait a full one)
-  if constexpr (PF == 2) __builtin_amdgcn_s_waitcnt(0x0F70);
-  for (int iz = z0; iz < z1; ++iz) {
-    if (!PF) load_bank(iz);
-    // ---- product + stage 2' (tiles k0 = TPW w + j; rows k1 = c; chunk h) ----
+  // ---- product + stage 2' (tiles k0 = TPW w + j; rows k1 = c; chunk h) ----
+  auto product_stage2 = [&]() {
     v8 av[TPW], avl[SPLIT ? TPW : 1];
 #pragma unroll
     for (int j = 0; j < TPW; ++j) {
@@ -459,11 +458,9 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
       // lane holds rows k1 = 4g + i, column n2 = c
       store_stage<H, SPLIT>(Ea, 16 * c + k0, g, dr, di);  // stage 1' butterfly (k0, n2 = c)
     }
-    if (PF == 2 && iz + 1 < z1) load_bank(iz + 1);
-    __syncthreads();
-    // vmcnt(0), expcnt and lgkmcnt at their maxima (no wait on them)
-    if constexpr (PF == 2) __builtin_amdgcn_s_waitcnt(0x0F70);
-    // ---- stage 1' (tiles n2 = TPW w + j; rows k0 = c) -------------------------
+  };
+  // ---- stage 1' (tiles n2 = TPW w + j; rows k0 = c) -------------------------
+  auto stage1 = [&]() {
 #pragma unroll
     for (int j = 0; j < TPW; ++j) {
       const int n2 = TPW * w + j;
@@ -474,10 +471,9 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
       // lane holds rows k0 = 4g + i, column n1 = c
       store_stage<H, SPLIT>(Eb, 16 * c + n2, g, dr, di);  // stage 0' butterfly (n1 = c, n2)
     }
-    if (iz > z0) store_staged(iz - 1);
-    if (PF == 1 && iz + 1 < z1) load_bank(iz + 1);
-    __syncthreads();
-    // ---- stage 0' (tiles n1 = TPW w + j; rows n2 = c) + |.|^2 -> staging ----
+  };
+  // ---- stage 0' (tiles n1 = TPW w + j; rows n2 = c) + |.|^2 -> staging ----
+  auto stage0 = [&]() {
 #pragma unroll
     for (int j = 0; j < TPW; ++j) {
       const int n1 = TPW * w + j;
@@ -490,10 +486,74 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
       for (int i = 0; i < 4; ++i) pw[i] = (dr[i] * dr[i] + di[i] * di[i]) * pscale;
       *reinterpret_cast<f4 *>(stg + 260 * c + 16 * n1 + 4 * g) = pw;
     }
-  }
-  if (z0 < z1) {
-    __syncthreads();
-    store_staged(z1 - 1);
+  };
+  // vmcnt(0), expcnt and lgkmcnt at their maxima (no wait on them)
+  auto drain_vm = [&]() { __builtin_amdgcn_s_waitcnt(0x0F70); };
+
+  // Per template: product + stage 2' | barrier | stage 1', stores of the
+  // previous template's staged powers | barrier | stage 0' into the staging
+  // buffer. Vector loads and stores share one counter, and with both kinds
+  // outstanding a wait for a load also waits for every store issued before
+  // it. PF == 1: the next bank row is loaded after the stores, so the wait
+  // for it (at the next product) comes a full phase after both were issued.
+  // PF == 2: the next bank row is loaded as soon as the product has read the
+  // current one, and everything outstanding is waited for explicitly at the
+  // start of the following phase, before the stores are issued: loads get one
+  // phase and the stores of the previous template two.
+  // PF == 3: as PF == 2, with the loop rotated so that stage 0' of one
+  // template and the product and stage 2' of the next share a phase without
+  // a branch between them (independent work the compiler can interleave),
+  // and the staged powers read before stage 1' (their LDS latency hidden
+  // behind it) and stored after it. In the flat batched form this was 1%
+  // faster than PF == 2 for FP16; in the persistent form, and with BF16, the
+  // rotated loop spills and is slower.
+  if constexpr (PF == 3) {
+    if (z0 < z1) {
+      load_bank(z0);
+      drain_vm();  // nothing outstanding on loop entry
+      product_stage2();
+      if (z0 + 1 < z1) load_bank(z0 + 1);
+      __syncthreads();
+      drain_vm();
+      stage1();
+      __syncthreads();
+      for (int iz = z0 + 1; iz < z1; ++iz) {
+        stage0();          // template iz - 1
+        product_stage2();  // template iz
+        if (iz + 1 < z1) load_bank(iz + 1);
+        __syncthreads();
+        drain_vm();
+        f4 v[TPW];
+        read_staged(v);    // powers of template iz - 1
+        stage1();
+        write_staged(iz - 1, v);
+        __syncthreads();
+      }
+      stage0();
+      __syncthreads();
+      store_staged(z1 - 1);
+    }
+  } else {
+    if (PF && z0 < z1) load_bank(z0);
+    // (PF == 2: nothing may be outstanding on entry, or the loads of the
+    // preheader would make every later wait a full one)
+    if constexpr (PF == 2) drain_vm();
+    for (int iz = z0; iz < z1; ++iz) {
+      if (!PF) load_bank(iz);
+      product_stage2();
+      if (PF == 2 && iz + 1 < z1) load_bank(iz + 1);
+      __syncthreads();
+      if constexpr (PF == 2) drain_vm();
+      stage1();
+      if (iz > z0) store_staged(iz - 1);
+      if (PF == 1 && iz + 1 < z1) load_bank(iz + 1);
+      __syncthreads();
+      stage0();
+    }
+    if (z0 < z1) {
+      __syncthreads();
+      store_staged(z1 - 1);
+    }
   }
 }
 
@@ -684,22 +744,19 @@ static OlsVariant make_mixed(const char *name, int precision) {
 }
 
 static const OlsVariant kMixedVariants[] = {
+    // the first of each precision and split form is its default
     make_mixed<_Float16, 2, true, 16, 8, false>("fp16_L4096_mfma_w16_pfw", 1),
-    make_mixed<_Float16, true, true, 16, 8, false>("fp16_L4096_mfma_w16_pf", 1),
-    make_mixed<_Float16, false, true, 16, 8, false>("fp16_L4096_mfma_w16", 1),
-    make_mixed<_Float16, true, true, 8, 4, false>("fp16_L4096_mfma_w8_pf", 1),
-    make_mixed<_Float16, false, true, 8, 4, false>("fp16_L4096_mfma_w8", 1),
-    make_mixed<_Float16, true, false, 16, 8, false>("fp16_L4096_mfma_w16_pf_ts", 1),
+    make_mixed<_Float16, 3, true, 16, 8, false>("fp16_L4096_mfma_w16_rot", 1),
+    make_mixed<_Float16, 1, true, 16, 8, false>("fp16_L4096_mfma_w16_pf", 1),
+    make_mixed<_Float16, 1, true, 8, 4, false>("fp16_L4096_mfma_w8_pf", 1),
+    make_mixed<_Float16, 1, false, 16, 8, false>("fp16_L4096_mfma_w16_pf_ts", 1),
     make_mixed<__bf16, 2, true, 16, 8, false>("bf16_L4096_mfma_w16_pfw", 2),
-    make_mixed<__bf16, true, true, 16, 8, false>("bf16_L4096_mfma_w16_pf", 2),
-    make_mixed<__bf16, true, true, 8, 4, false>("bf16_L4096_mfma_w8_pf", 2),
+    make_mixed<__bf16, 1, true, 8, 4, false>("bf16_L4096_mfma_w8_pf", 2),
     // hi + lo split products (FDAS_FLAG_SPLIT)
     make_mixed<_Float16, 2, true, 16, 4, true>("fp16_L4096_mfma_split_w16_pfw", 1),
     make_mixed<__bf16, 2, true, 16, 4, true>("bf16_L4096_mfma_split_w16_pfw", 2),
-    make_mixed<_Float16, false, true, 16, 4, true>("fp16_L4096_mfma_split_w16", 1),
-    make_mixed<_Float16, true, true, 16, 4, true>("fp16_L4096_mfma_split_w16_pf", 1),
-    make_mixed<__bf16, false, true, 16, 4, true>("bf16_L4096_mfma_split_w16", 2),
-    make_mixed<__bf16, true, true, 16, 4, true>("bf16_L4096_mfma_split_w16_pf", 2),
+    make_mixed<__bf16, 3, true, 16, 4, true>("bf16_L4096_mfma_split_w16_rot", 2),
+    make_mixed<__bf16, 0, true, 16, 4, true>("bf16_L4096_mfma_split_w16", 2),
 };
 
 const OlsVariant *mixed_variants(int *count) {
