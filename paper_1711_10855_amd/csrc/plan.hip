@@ -44,7 +44,10 @@ struct fdas_plan_s {
   int last_zpb = 0;         // templates per unit of the last single-series launch
 };
 
-static constexpr size_t kMaxGraphs = 8;
+// Captured batch layouts kept per plan (least recently used evicted): enough
+// for a workload run in many waves to replay every wave's graph, since a
+// re-capture synchronises the stream and uploads the descriptors again.
+static constexpr size_t kMaxGraphs = 64;
 
 namespace fdas {
 

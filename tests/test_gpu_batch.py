@@ -167,3 +167,34 @@ def test_wide_batch_workload_sample(gpu, prec, split, tol):
         err = float(np.max(np.abs(o[iz, r] - ref)) / ref.max())
         print(f"{prec} series nbins={sp.nbins}: {err:.3e}")
         assert err <= tol
+
+
+def test_many_batch_layouts_replay_in_turn(gpu):
+    """Twelve distinct batch layouts, each called three times in turn, give
+    the same planes every time (each layout keeps its own captured graph and
+    descriptor table)."""
+    import torch
+    layouts = []
+    for k in range(12):
+        specs = [(300 + 97 * k, 16.0, 0), (1 + k, 8.0, 1), (2000 - 50 * k, 4.0, 0)]
+        spectra, zmaxs, outs = make_batch(16.0, 2.0, specs)
+        layouts.append(([to_dev(a) for a in spectra], zmaxs, outs))
+    with gpu.Plan(16.0, 2.0, 64, 256) as p:
+        first = []
+        for rep in range(3):
+            for k, (dev, zmaxs, outs) in enumerate(layouts):
+                for o in outs:
+                    o.fill_(-3.0)
+                p.convolve_batch(dev, zmaxs, outs)
+                torch.cuda.synchronize()
+                got = [o.cpu().numpy() for o in outs]
+                if rep == 0:
+                    first.append(got)
+                    for a, z, g in zip(dev, zmaxs, got):
+                        row0 = int(round((16.0 - z) / 2.0))
+                        full = p.convolve(a).cpu().numpy()[row0:row0 + g.shape[0]]
+                        assert np.max(np.abs(g[:, :a.numel()] - full)) <= \
+                            1e-6 * max(1.0, float(full.max())), k
+                else:
+                    for g, f in zip(got, first[k]):
+                        assert np.array_equal(g, f), (rep, k)
