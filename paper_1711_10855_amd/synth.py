@@ -52,7 +52,7 @@ class Workload:
     dz: float
     m: int
     seg_len: int
-    precision: str = "fp32"
+    precision: str = "fp32"   # the workload's main form (bench.py times several)
     nseries: int = 1
     description: str = ""
     extra: dict = field(default_factory=dict)
@@ -86,10 +86,12 @@ WORKLOADS = {
         description="fp32-paper inputs, FP16 storage and MFMA DFT stages"),
     "batch-mixed-wide": Workload(
         "batch-mixed-wide", 5, 1 << 22, 200.0, 2.0, 512, 4096, nseries=256,
-        precision="bf16",
+        precision="fp16",
         description="256 series of 2^22 samples, 0-3 chirps, z in [-200,200] "
                     "step 2 (201 templates, width 512), segment FFT 4096 "
-                    "(8192 and 16384 ran slower in plain FP32)"),
+                    "(8192 and 16384 ran slower in plain FP32); the 16-bit "
+                    "form that holds 1e-3 unsplit is FP16 (BF16 needs the "
+                    "hi+lo split)"),
 }
 
 
