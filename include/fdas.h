@@ -67,6 +67,8 @@ extern "C" {
                                  integer r and row 2i + 1 the same z_i at
                                  r + 1/2, from the same m + 1 bins
                                  [r - m/2, r + m/2] (offsets q - 1/2) */
+#define FDAS_FLAG_BANK 8u     /* fdas_make_templates: the Fourier-domain bank
+                                 instead of the templates (ignored elsewhere) */
 
 /* Filter-bank parameters.
  *   zmax, dz  : z grid z_i = -zmax + i*dz; zmax >= 0, dz > 0, 2*zmax/dz an
@@ -138,10 +140,18 @@ int fdas_resolve_params(const fdas_params *in, fdas_params *out);
  * eq. 2), in FP64 on the device.
  *   templates : device complex128 [nz][m+1], element [i][j] = H_{z_i}(j - m/2),
  *               or NULL to only query the size.
+ *               With FDAS_FLAG_BANK in p->flags: the template bank the
+ *               overlap-and-save product multiplies by instead, device
+ *               complex64 [nz][L] in natural frequency order,
+ *               T_i[k] = conj(sum_q H_{z_i}(q) exp(-2 pi i (q mod L) k / L)) / L
+ *               (an FP64 direct sum with exact phase reduction, rounded to
+ *               FP32; L = seg_len as resolved, which must not be left to the
+ *               autotuner). This form allocates an FP64 temporary of
+ *               nz (m+1) 16 bytes and synchronises `stream`.
  *   bytes     : in/out. On return holds the required size in bytes. When
  *               templates != NULL, *bytes on entry must be >= that size.
- * Parameters are resolved as in fdas_resolve_params. The call is
- * asynchronous on `stream`.                                                  */
+ * Parameters are resolved as in fdas_resolve_params (nz doubles with
+ * FDAS_FLAG_INTERBIN). Otherwise asynchronous on `stream`, no allocation.    */
 int fdas_make_templates(const fdas_params *p, void *templates, size_t *bytes,
                         void *stream);
 

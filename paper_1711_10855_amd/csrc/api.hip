@@ -60,7 +60,7 @@ int resolve_params(const fdas_params *in, fdas_params *out, int *nz_out) {
   fdas_params p = *in;
   const int ntz = validate_grid(p.zmax, p.dz);
   if (ntz < 0) return ntz;
-  if (p.flags & ~(FDAS_FLAG_SPLIT | FDAS_FLAG_AUTOTUNE | FDAS_FLAG_INTERBIN))
+  if (p.flags & ~(FDAS_FLAG_SPLIT | FDAS_FLAG_AUTOTUNE | FDAS_FLAG_INTERBIN | FDAS_FLAG_BANK))
     return set_error(FDAS_ERR_INVALID, "unknown flag bits 0x%x", p.flags);
   // bank and plane rows: one per trial drift, two with half-bin rows
   const int nz = (p.flags & FDAS_FLAG_INTERBIN) ? 2 * ntz : ntz;
@@ -210,7 +210,10 @@ int fdas_make_templates(const fdas_params *p, void *templates, size_t *bytes, vo
   int st = resolve_params(p, &r, &nz);
   if (st) return st;
   if (!bytes) return set_error(FDAS_ERR_INVALID, "null bytes pointer");
-  const size_t need = (size_t)nz * (size_t)(r.m + 1) * 16;
+  const bool bank = (r.flags & FDAS_FLAG_BANK) != 0;
+  if (bank && r.seg_len <= r.m)
+    return set_error(FDAS_ERR_INVALID, "the bank needs a segment length (not autotuned)");
+  const size_t need = bank ? (size_t)nz * (size_t)r.seg_len * 8 : (size_t)nz * (size_t)(r.m + 1) * 16;
   if (!templates) {
     *bytes = need;
     return FDAS_OK;
@@ -220,10 +223,34 @@ int fdas_make_templates(const fdas_params *p, void *templates, size_t *bytes, vo
     *bytes = need;
     return set_error(FDAS_ERR_INVALID, "templates buffer holds %zu bytes, need %zu", have, need);
   }
+  if (reinterpret_cast<uintptr_t>(templates) & 7)
+    return set_error(FDAS_ERR_INVALID, "misaligned templates buffer");
   *bytes = need;
-  hipError_t e = launch_templates(templates, nz, r.m, r.zmax, r.dz,
-                                  (r.flags & FDAS_FLAG_INTERBIN) ? 1 : 0, (hipStream_t)stream);
-  if (e != hipSuccess) return hip_error(e, "template kernel launch");
+  const int interbin = (r.flags & FDAS_FLAG_INTERBIN) ? 1 : 0;
+  const hipStream_t s = (hipStream_t)stream;
+  if (!bank) {
+    const hipError_t e = launch_templates(templates, nz, r.m, r.zmax, r.dz, interbin, s);
+    if (e != hipSuccess) return hip_error(e, "template kernel launch");
+    return FDAS_OK;
+  }
+  // natural frequency order: one radix-L "stage" on one thread maps slot e to
+  // frequency e
+  LayoutDesc nat{};
+  nat.L = r.seg_len;
+  nat.T = 1;
+  nat.E = r.seg_len;
+  nat.P = 1;
+  nat.R[0] = r.seg_len;
+  for (int i = 1; i < kMaxStages; ++i) nat.R[i] = 1;
+  void *h = nullptr;
+  hipError_t e = hipMalloc(&h, (size_t)nz * (size_t)(r.m + 1) * 16);
+  if (e != hipSuccess) return set_error(FDAS_ERR_NOMEM, "template temporary: %s", hipGetErrorString(e));
+  e = launch_templates(h, nz, r.m, r.zmax, r.dz, interbin, s);
+  if (e == hipSuccess) e = launch_bank(static_cast<c32 *>(templates), h, nz, r.m, nat, s);
+  const hipError_t e2 = hipStreamSynchronize(s);
+  (void)hipFree(h);
+  if (e != hipSuccess) return hip_error(e, "bank kernel launch");
+  if (e2 != hipSuccess) return hip_error(e2, "bank kernels");
   return FDAS_OK;
 }
 

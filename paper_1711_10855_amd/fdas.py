@@ -30,6 +30,7 @@ PRECISIONS = {"fp32": FP32, "fp16": MIXED_FP16, "bf16": MIXED_BF16}
 FLAG_SPLIT = 1
 FLAG_AUTOTUNE = 2
 FLAG_INTERBIN = 4
+FLAG_BANK = 8
 
 EXPORTS = (
     "fdas_plane_rows", "fdas_resolve_params", "fdas_make_templates", "fdas_plan",
@@ -214,6 +215,23 @@ def make_templates(zmax, dz, m=0, flags=0):
     out = torch.empty((nz, r.m + 1), dtype=torch.complex128, device="cuda")
     _check(load().fdas_make_templates(C.byref(p), C.c_void_p(out.data_ptr()), C.byref(nbytes),
                                       _stream()), "fdas_make_templates")
+    return out
+
+
+def make_bank(zmax, dz, m=0, seg_len=0, flags=0):
+    """The Fourier-domain template bank T_i[k], complex64 tensor [rows, L] in
+    natural frequency order on the current device (FP64 direct sums rounded
+    to FP32; fdas_make_templates with FLAG_BANK)."""
+    import torch
+    p = params(zmax, dz, m, seg_len, "fp32", flags | FLAG_BANK)
+    nbytes = C.c_size_t(0)
+    _check(load().fdas_make_templates(C.byref(p), None, C.byref(nbytes), None),
+           "fdas_make_templates(bank size)")
+    r = resolve(zmax, dz, m, seg_len, "fp32", flags)
+    nz = plane_rows(zmax, dz, flags)
+    out = torch.empty((nz, r.seg_len), dtype=torch.complex64, device="cuda")
+    _check(load().fdas_make_templates(C.byref(p), C.c_void_p(out.data_ptr()), C.byref(nbytes),
+                                      _stream()), "fdas_make_templates(bank)")
     return out
 
 

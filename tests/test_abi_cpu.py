@@ -216,3 +216,17 @@ def test_peaks_workspace_and_host_checks(lib):
     assert lib.fdas_peaks_workspace_bytes(1024) == 1024 * 16 + 2048 * 12
     assert lib.fdas_convolve_peaks(None, C.c_void_p(8), 10, 1.0, C.c_void_p(16), 1 << 20, 100,
                                    C.c_void_p(16), 10, C.c_void_p(8), None) == fdas.ERR_INVALID
+
+
+def test_bank_size_query_needs_no_device(lib):
+    """fdas_make_templates with FDAS_FLAG_BANK: complex64 [nz][L]; the segment
+    length must be known (not left to the autotuner)."""
+    n = C.c_size_t(0)
+    p = fdas.params(16, 2, 64, 256, "fp32", fdas.FLAG_BANK)
+    assert lib.fdas_make_templates(C.byref(p), None, C.byref(n), None) == 0
+    assert n.value == 17 * 256 * 8
+    p = fdas.params(16, 2, 64, 0, "fp32", fdas.FLAG_BANK | fdas.FLAG_INTERBIN)
+    assert lib.fdas_make_templates(C.byref(p), None, C.byref(n), None) == 0
+    assert n.value == 34 * fdas.resolve(16, 2, 64).seg_len * 8
+    p = fdas.params(16, 2, 64, 0, "fp32", fdas.FLAG_BANK | fdas.FLAG_AUTOTUNE)
+    assert lib.fdas_make_templates(C.byref(p), None, C.byref(n), None) == fdas.ERR_INVALID

@@ -57,6 +57,21 @@ def test_bank_matches_oracle(gpu, L, m, zmax):
     assert np.max(np.abs(dev - ref)) <= 1.2e-7 * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("L,m,zmax,flags", [(256, 64, 16, 0), (4096, 512, 200, 0),
+                                            (1024, 64, 8, 4)])
+def test_make_templates_bank_form(gpu, L, m, zmax, flags):
+    """fdas_make_templates with FDAS_FLAG_BANK gives the Fourier-domain bank in
+    natural order: the oracle's FP64 bank to FP32 rounding, and exactly the
+    values an FP32 plan of the same length stores."""
+    bank = gpu.make_bank(zmax, 2.0, m, L, flags).cpu().numpy()
+    _, h = oracle.templates64(zmax, 2.0, m, bool(flags & gpu.FLAG_INTERBIN))
+    ref = oracle.bank_natural(h, m, L)
+    assert bank.shape == ref.shape
+    assert np.max(np.abs(bank.astype(np.complex128) - ref)) <= 1.2e-7 * np.max(np.abs(ref))
+    with gpu.Plan(zmax, 2.0, m, L, "fp32", flags) as p:
+        assert np.array_equal(p.bank().cpu().numpy(), bank)
+
+
 def test_workload1_full_plane(gpu):
     a, _ = synth.single_series("fp32-small")
     ref = oracle.plane_direct(a, 16.0, 2.0, 64)
