@@ -17,7 +17,8 @@ holds the others with their speed-up over plain FP32.
 
 Other workloads (--workload): fp32-small, fp32-paper (one 2^21-bin plane,
 101 templates), mixed-paper, batch-fp32 (512 series of uneven length,
-per-series zmax; the FP32 plan's segment length is autotuned).
+per-series zmax). On the batched workloads the FP32 plan is autotuned
+(segment length, variant, templates per unit).
 
 Errors (`error_vs_oracle`, per form): every series of a batch is checked at
 sampled plane points (around each injected signal, at both edges and
@@ -471,8 +472,10 @@ def bench_batch(args, forms, line):
         prec, flags = FORMS[form]
         seg_len = form_seg_len(form, w, args)
         fl = flags | ib
-        if prec == "fp32" and args.workload == "batch-fp32" and not args.seg_len:
-            seg_len, fl = 0, fl | AUTOTUNE  # autotuned segment length (512 .. 8192)
+        if prec == "fp32" and not args.seg_len:
+            # the FP32 baseline at its best: segment length, variant and unit
+            # size chosen by the autotuner (the matrix-core forms have one length)
+            seg_len, fl = 0, fl | AUTOTUNE
         plan = fdas.Plan(w.zmax, w.dz, w.m, seg_len, prec, fl, device=0)
         log(f"{form}: plan {plan.info.kernel} L={plan.info.seg_len} "
             f"({plan.info.plan_ms:.0f} ms); timing {len(b.waves)} waves x {args.steps} steps")
