@@ -18,7 +18,8 @@ holds the others with their speed-up over plain FP32.
 Other workloads (--workload): fp32-small, fp32-paper (one 2^21-bin plane,
 101 templates), mixed-paper, batch-fp32 (512 series of uneven length,
 per-series zmax). On the batched workloads the FP32 plan is autotuned
-(segment length, variant, templates per unit).
+(segment length, variant, templates per unit); on a single series its
+variant and unit size are, at the workload's segment length.
 
 Errors (`error_vs_oracle`, per form): every series of a batch is checked at
 sampled plane points (around each injected signal, at both edges and
@@ -586,8 +587,10 @@ def bench_single(args, forms, line):
     results = {}
     for form in forms:
         prec, flags = FORMS[form]
+        # FP32 at the workload's segment length, variant and unit size tuned
+        tune = AUTOTUNE if prec == "fp32" and not args.variant and not args.zpb else 0
         results[form] = run_single(a_dev, w.zmax, w.dz, w.m, form_seg_len(form, w, args), prec,
-                                   flags | ib, args, keep_cols=keep)
+                                   flags | ib | tune, args, keep_cols=keep)
         log(f"{form}: {results[form]['ms']:.4f} ms per step")
     head = forms[0]
     r = results[head]

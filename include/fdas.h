@@ -116,8 +116,9 @@ typedef struct {
   int precision;
   unsigned flags;
   int threads;         /* threads per segment in the hot kernel              */
-  int templates_per_block; /* of the last fdas_convolve launch (before the
-                              first one: the plan's default)              */
+  int templates_per_block; /* of the last fdas_convolve launch, or the largest
+                              work unit of the last fdas_convolve_batch
+                              (before either: the plan's default)         */
   int segments_per_block;
   size_t bank_bytes;   /* device bytes of the Fourier-domain template bank   */
   double plan_ms;      /* wall time of fdas_plan (templates + bank)          */

@@ -41,7 +41,7 @@ struct fdas_plan_s {
   int cus = 0;
   bool zpb_forced = false;  // FDAS_ZPB or the autotuner fixed it
   int slots = 0;            // concurrently resident blocks of the grid kernel
-  int last_zpb = 0;         // templates per unit of the last single-series launch
+  int last_zpb = 0;         // templates per unit of the last launch (a batch: its largest)
 };
 
 // Captured batch layouts kept per plan (least recently used evicted): enough
@@ -637,10 +637,13 @@ int plan_convolve_batch(fdas_plan_t pl, const fdas_series *series, int nseries, 
     nsb += (desc[i].nseg + G - 1) / G;
   }
   const int zpb = batch_zpb(pl, nsb);
+  int most = 0;  // templates per unit of the largest unit, for plan info
   for (int i = 0; i < nseries; ++i) {
     const int ng = (desc[i].nz + zpb - 1) / zpb;
     desc[i].zpb = (desc[i].nz + ng - 1) / ng;
+    most = std::max(most, desc[i].zpb);
   }
+  pl->last_zpb = most;
   std::vector<int> order(nseries);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
