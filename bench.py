@@ -281,10 +281,17 @@ def _time(fn, steps, warmup, warmup_s, stream):
 
 
 def form_seg_len(form, w, args):
-    prec = FORMS[form][0]
-    if prec != "fp32":
-        return 4096
-    return args.seg_len or w.seg_len
+    """Segment length of a form on workload w: FP32 at --seg-len or the
+    workload's; the matrix-core forms at the workload's length where that
+    form is compiled for it (2048 and 4096; the split forms 4096 only),
+    else 4096."""
+    prec, flags = FORMS[form]
+    if prec == "fp32":
+        return args.seg_len or w.seg_len
+    from paper_1711_10855_amd import fdas
+    split = bool(flags & SPLIT)
+    names = fdas.kernel_variants(w.seg_len, prec)
+    return w.seg_len if any(("_split" in n) == split for n in names) else 4096
 
 
 class Batch:
@@ -475,7 +482,8 @@ def bench_batch(args, forms, line):
         fl = flags | ib
         if prec == "fp32" and not args.seg_len:
             # the FP32 baseline at its best: segment length, variant and unit
-            # size chosen by the autotuner (the matrix-core forms have one length)
+            # size chosen by the autotuner (the matrix-core forms run at the
+            # workload's length, 4096 on the batched mixed workload)
             seg_len, fl = 0, fl | AUTOTUNE
         plan = fdas.Plan(w.zmax, w.dz, w.m, seg_len, prec, fl, device=0)
         log(f"{form}: plan {plan.info.kernel} L={plan.info.seg_len} "

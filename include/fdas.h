@@ -76,10 +76,12 @@ extern "C" {
  *   m         : even, >= 2; taps q in [-m/2, m/2] (m + 1 bins, eq. 2).
  *               0 selects the default nextpow2(2*zmax + 32), at least 8.
  *   seg_len   : overlap-and-save segment (FFT) length L, a power of two in
- *               [256, 16384] with L > m (mixed precisions: 4096). 0 selects
- *               the default (FP32: nextpow2(8 m) clamped to [256, 16384];
- *               mixed: 4096), or with FDAS_FLAG_AUTOTUNE lets the tuner
- *               choose among compiled lengths with L - m >= L / 2.
+ *               [256, 16384] with L > m (mixed precisions: 2048 or 4096,
+ *               with FDAS_FLAG_SPLIT 4096; others give
+ *               FDAS_ERR_UNSUPPORTED). 0 selects the default (FP32:
+ *               nextpow2(8 m) clamped to [256, 16384]; mixed: 4096), or
+ *               with FDAS_FLAG_AUTOTUNE lets the tuner choose among
+ *               compiled lengths with L - m >= L / 2.
  *   precision : FDAS_FP32 / FDAS_MIXED_FP16 / FDAS_MIXED_BF16.
  *   flags     : FDAS_FLAG_* bits.                                           */
 typedef struct {

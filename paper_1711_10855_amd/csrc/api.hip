@@ -88,9 +88,12 @@ int resolve_params(const fdas_params *in, fdas_params *out, int *nz_out) {
   if ((p.seg_len & (p.seg_len - 1)) || p.seg_len < 256 || p.seg_len > 16384)
     return set_error(FDAS_ERR_UNSUPPORTED, "seg_len %d: compiled lengths are powers of two in [256, 16384]",
                      p.seg_len);
-  if (p.precision != FDAS_FP32 && !mixed_supported(p.seg_len))
-    return set_error(FDAS_ERR_UNSUPPORTED, "precision %d is not available for seg_len %d",
-                     p.precision, p.seg_len);
+  if (p.precision != FDAS_FP32) {
+    const int split = (p.flags & FDAS_FLAG_SPLIT) ? 1 : 0;
+    if (!mixed_supported(p.seg_len, split))
+      return set_error(FDAS_ERR_UNSUPPORTED, "precision %d%s is not available for seg_len %d",
+                       p.precision, split ? " with the split form" : "", p.seg_len);
+  }
   *out = p;
   if (nz_out) *nz_out = nz;
   return FDAS_OK;

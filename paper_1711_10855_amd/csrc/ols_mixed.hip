@@ -39,7 +39,9 @@
 
 #include <cstdint>
 #include <cstdlib>
+#include <iterator>
 #include <type_traits>
+#include <vector>
 
 #include "fft_radix.hpp"
 #include "ols_variants.hpp"
@@ -759,9 +761,18 @@ static const OlsVariant kMixedVariants[] = {
     make_mixed<__bf16, 0, true, 16, 4, true>("bf16_L4096_mfma_split_w16", 2),
 };
 
+// Every matrix-core variant: the 4096-point ones above, then the 2048-point
+// kernel's.
 const OlsVariant *mixed_variants(int *count) {
-  *count = (int)(sizeof(kMixedVariants) / sizeof(kMixedVariants[0]));
-  return kMixedVariants;
+  static const std::vector<OlsVariant> all = [] {
+    std::vector<OlsVariant> v(std::begin(kMixedVariants), std::end(kMixedVariants));
+    int n = 0;
+    const OlsVariant *w = mixed2048_variants(&n);
+    v.insert(v.end(), w, w + n);
+    return v;
+  }();
+  *count = (int)all.size();
+  return all.data();
 }
 
 // ---- plan-time: 16-bit planar bank in the X layout ------------------------
@@ -859,10 +870,12 @@ __global__ void mixed_consts_kernel(unsigned char *__restrict__ out, int split) 
 }
 
 size_t mixed_consts_bytes(int L, int split) {
+  if (L == 2048) return split ? 0 : mixed2048_consts_bytes();
   return L == 4096 ? (size_t)kConstBytes * (split ? 2 : 1) : 0;
 }
 
 hipError_t launch_mixed_consts(void *out, int L, int precision, int split, hipStream_t s) {
+  if (L == 2048 && !split) return launch_mixed2048_consts(out, precision, s);
   if (L != 4096) return hipErrorInvalidValue;
   if (precision == 2)
     hipLaunchKernelGGL(mixed_consts_kernel<__bf16>, dim3(8), dim3(256), 0, s,
@@ -875,6 +888,8 @@ hipError_t launch_mixed_consts(void *out, int L, int precision, int split, hipSt
 
 hipError_t launch_bank_mixed(void *bank, const void *h, int nz, int m, int L, int precision,
                              int split, hipStream_t s) {
+  if (L == 2048)
+    return split ? hipErrorInvalidValue : launch_bank_mixed2048(bank, h, nz, m, precision, s);
   const long n = (long)nz * L;
   const dim3 grid((unsigned)((n + 255) / 256));
   if (precision == 2)
@@ -889,6 +904,8 @@ hipError_t launch_bank_mixed(void *bank, const void *h, int nz, int m, int L, in
 
 hipError_t launch_bank_mixed_natural(c32 *dst, const void *bank, int nz, int L, int precision,
                                      int split, hipStream_t s) {
+  if (L == 2048)
+    return split ? hipErrorInvalidValue : launch_bank_mixed2048_natural(dst, bank, nz, precision, s);
   const long n = (long)nz * L;
   const dim3 grid((unsigned)((n + 255) / 256));
   if (precision == 2)

@@ -118,6 +118,15 @@ hipError_t launch_mixed_consts(void *out, int L, int precision, int split, hipSt
 hipError_t launch_bank_mixed_natural(c32 *dst, const void *bank, int nz, int L, int precision,
                                      int split, hipStream_t s);
 
+// The 2048-point matrix-core kernel (FP16 and BF16, no split form).
+const OlsVariant *mixed2048_variants(int *count);
+size_t mixed2048_consts_bytes();
+hipError_t launch_mixed2048_consts(void *out, int precision, hipStream_t s);
+hipError_t launch_bank_mixed2048(void *bank, const void *h, int nz, int m, int precision,
+                                 hipStream_t s);
+hipError_t launch_bank_mixed2048_natural(c32 *dst, const void *bank, int nz, int precision,
+                                         hipStream_t s);
+
 hipError_t launch_reset_counter(unsigned long long *counter, hipStream_t s);
 hipError_t launch_templates(void *out, int rows, int m, double zmax, double dz, int interbin,
                             hipStream_t s);

@@ -51,11 +51,11 @@ static constexpr size_t kMaxGraphs = 64;
 
 namespace fdas {
 
-bool mixed_supported(int seg_len) {
+bool mixed_supported(int seg_len, int split) {
   int n = 0;
   const OlsVariant *v = mixed_variants(&n);
   for (int i = 0; i < n; ++i)
-    if (v[i].L == seg_len) return true;
+    if (v[i].L == seg_len && v[i].split == split) return true;
   return false;
 }
 

@@ -12,7 +12,7 @@ int set_error(int status, const char *fmt, ...);
 int hip_error(hipError_t e, const char *what);
 int resolve_params(const fdas_params *in, fdas_params *out, int *nz_out);
 int default_seg_len(int m, int nz, int precision);
-bool mixed_supported(int seg_len);
+bool mixed_supported(int seg_len, int split);
 
 int build_plan(fdas_plan_t *out, const fdas_params &p, int nz, int device, hipStream_t s);
 void plan_info(fdas_plan_t plan, fdas_plan_info *info);

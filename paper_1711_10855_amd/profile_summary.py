@@ -29,12 +29,16 @@ ROOT = os.path.dirname(HERE)
 FP32_SOURCES = ["csrc/ols_fp32.hip", "csrc/fft_radix.hpp", "csrc/fft_block.hpp",
                 "csrc/layout.hpp", "csrc/ols_variants.hpp"]
 MIXED_SOURCES = ["csrc/ols_mixed.hip", "csrc/fft_radix.hpp", "csrc/ols_variants.hpp"]
+MIXED2048_SOURCES = ["csrc/ols_mixed2048.hip", "csrc/fft_radix.hpp", "csrc/ols_variants.hpp"]
 
 
 def kernel_sources(kernel: str) -> list[str]:
     """Source files of a hot-kernel variant, by its name (fp32_* variants are
-    the FP32 kernels, the others the matrix-core kernels)."""
-    return FP32_SOURCES if kernel.startswith("fp32_") else MIXED_SOURCES
+    the FP32 kernels, *_L2048_mfma_* the 2048-point matrix-core kernel, the
+    others the 4096-point matrix-core kernels)."""
+    if kernel.startswith("fp32_"):
+        return FP32_SOURCES
+    return MIXED2048_SOURCES if "_L2048_mfma" in kernel else MIXED_SOURCES
 
 
 def source_hash(kernel: str) -> str:

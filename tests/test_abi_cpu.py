@@ -133,6 +133,21 @@ def test_kernel_variant_listing():
     assert (r.seg_len, r.flags) == (4096, fdas.FLAG_SPLIT)
 
 
+def test_matrix_core_lengths():
+    """The matrix-core kernels exist at 4096 (all forms) and 2048 (FP16 and
+    BF16 without the split form); other lengths are refused on the host."""
+    for prec in ("fp16", "bf16"):
+        assert fdas.kernel_variants(2048, prec) == [f"{prec}_L2048_mfma_w16"]
+        assert fdas.resolve(100, 2, 256, 2048, prec).seg_len == 2048
+        with pytest.raises(fdas.FdasError) as e:
+            fdas.resolve(100, 2, 256, 2048, prec, fdas.FLAG_SPLIT)
+        assert e.value.status == fdas.ERR_UNSUPPORTED and "split" in fdas.last_error()
+        for L in (1024, 8192):
+            with pytest.raises(fdas.FdasError) as e:
+                fdas.resolve(100, 2, 256, L, prec)
+            assert e.value.status == fdas.ERR_UNSUPPORTED
+
+
 def test_fft_variant_listing():
     names = fdas.fft_variants()
     assert len(names) >= 10

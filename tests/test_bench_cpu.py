@@ -101,3 +101,20 @@ def test_pick_series():
     nb = [s.nbins for s in specs]
     assert nb.index(min(nb)) in pick and nb.index(max(nb)) in pick
     assert {specs[i].zmax for i in pick} == {32.0, 64.0, 100.0}
+
+
+def test_profile_rows_hash_their_own_kernel_sources():
+    from paper_1711_10855_amd import profile_summary as ps
+    assert "csrc/ols_fp32.hip" in ps.kernel_sources("fp32_L2048_t128_r8.16.16_o2")
+    assert "csrc/ols_mixed.hip" in ps.kernel_sources("fp16_L4096_mfma_w16_pfw")
+    assert "csrc/ols_mixed2048.hip" in ps.kernel_sources("fp16_L2048_mfma_w16")
+    assert ps.source_hash("fp16_L2048_mfma_w16") != ps.source_hash("fp16_L4096_mfma_w16_pfw")
+
+
+def test_matrix_core_forms_run_at_the_workloads_length():
+    import bench
+    args = bench.parse([])
+    paper, wide = synth.WORKLOADS["fp32-paper"], synth.WORKLOADS["batch-mixed-wide"]
+    assert bench.form_seg_len("fp16", paper, args) == 2048
+    assert bench.form_seg_len("bf16-split", paper, args) == 4096   # split: 4096 only
+    assert bench.form_seg_len("fp16", wide, args) == 4096
