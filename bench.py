@@ -84,6 +84,9 @@ def parse(argv=None):
                          f"single series: {DEFAULT_FORMS['single']}")
     ap.add_argument("--variant", default=None, help="force a compiled kernel variant")
     ap.add_argument("--zpb", type=int, default=None, help="templates per work unit")
+    ap.add_argument("--mixed-seg-len", type=int, default=None,
+                    help="segment length of the matrix-core forms (default: the workload's "
+                         "where that form is compiled for it, else 4096)")
     ap.add_argument("--seg-len", type=int, default=None,
                     help="FP32 segment length (default: the workload's; batch-fp32 autotunes)")
     ap.add_argument("--interbin", action="store_true",
@@ -288,6 +291,8 @@ def form_seg_len(form, w, args):
     prec, flags = FORMS[form]
     if prec == "fp32":
         return args.seg_len or w.seg_len
+    if args.mixed_seg_len:
+        return args.mixed_seg_len
     from paper_1711_10855_amd import fdas
     split = bool(flags & SPLIT)
     names = fdas.kernel_variants(w.seg_len, prec)

@@ -509,6 +509,10 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
   // behind it) and stored after it. In the flat batched form this was 1%
   // faster than PF == 2 for FP16; in the persistent form, and with BF16, the
   // rotated loop spills and is slower.
+  // PF == 4: loads as PF == 2, no explicit drain: the compiler waits for the
+  // bank row at the next product, stores of the same template included. On
+  // the unsplit forms 2-3% faster than PF == 2 on the wide batch and the
+  // paper-scale plane; on the split form 1% slower.
   if constexpr (PF == 3) {
     if (z0 < z1) {
       load_bank(z0);
@@ -543,7 +547,7 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
     for (int iz = z0; iz < z1; ++iz) {
       if (!PF) load_bank(iz);
       product_stage2();
-      if (PF == 2 && iz + 1 < z1) load_bank(iz + 1);
+      if ((PF == 2 || PF == 4) && iz + 1 < z1) load_bank(iz + 1);
       __syncthreads();
       if constexpr (PF == 2) drain_vm();
       stage1();
@@ -747,16 +751,19 @@ static OlsVariant make_mixed(const char *name, int precision) {
 
 static const OlsVariant kMixedVariants[] = {
     // the first of each precision and split form is its default
+    make_mixed<_Float16, 4, true, 16, 8, false>("fp16_L4096_mfma_w16_pfn", 1),
     make_mixed<_Float16, 2, true, 16, 8, false>("fp16_L4096_mfma_w16_pfw", 1),
     make_mixed<_Float16, 3, true, 16, 8, false>("fp16_L4096_mfma_w16_rot", 1),
     make_mixed<_Float16, 1, true, 16, 8, false>("fp16_L4096_mfma_w16_pf", 1),
     make_mixed<_Float16, 1, true, 8, 4, false>("fp16_L4096_mfma_w8_pf", 1),
     make_mixed<_Float16, 1, false, 16, 8, false>("fp16_L4096_mfma_w16_pf_ts", 1),
+    make_mixed<__bf16, 4, true, 16, 8, false>("bf16_L4096_mfma_w16_pfn", 2),
     make_mixed<__bf16, 2, true, 16, 8, false>("bf16_L4096_mfma_w16_pfw", 2),
     make_mixed<__bf16, 1, true, 8, 4, false>("bf16_L4096_mfma_w8_pf", 2),
     // hi + lo split products (FDAS_FLAG_SPLIT)
     make_mixed<_Float16, 2, true, 16, 4, true>("fp16_L4096_mfma_split_w16_pfw", 1),
     make_mixed<__bf16, 2, true, 16, 4, true>("bf16_L4096_mfma_split_w16_pfw", 2),
+    make_mixed<__bf16, 4, true, 16, 4, true>("bf16_L4096_mfma_split_w16_pfn", 2),
     make_mixed<__bf16, 3, true, 16, 4, true>("bf16_L4096_mfma_split_w16_rot", 2),
     make_mixed<__bf16, 0, true, 16, 4, true>("bf16_L4096_mfma_split_w16", 2),
 };
