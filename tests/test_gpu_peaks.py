@@ -52,7 +52,9 @@ def to_grid_index(row, r, interbin):
                                                 ("fp32", 1024, 64, 4, 1e-4),
                                                 ("fp16", 4096, 64, 0, 1e-3),
                                                 ("bf16", 4096, 64, 1, 1e-3),
-                                                ("fp16", 4096, 128, 4, 1e-3)])
+                                                ("fp16", 4096, 128, 4, 1e-3),
+                                                ("fp16", 2048, 64, 0, 1e-3),
+                                                ("fp16", 2048, 128, 4, 1e-3)])
 def test_peaks_match_oracle(gpu, prec, L, m, flags, tol):
     a = synth.small_random_spectrum(20000, seed=90)
     a[7000:7010] *= 6.0                       # strong bins among the noise

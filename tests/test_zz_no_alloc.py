@@ -41,7 +41,8 @@ def run(gpu, plan, specs, seed, noalloc):
 
 
 @pytest.mark.parametrize("prec,L,m,persistent", [("fp32", 256, 64, "0"), ("fp32", 1024, 128, "1"),
-                                                 ("fp16", 4096, 64, "0"), ("fp16", 4096, 64, "1")])
+                                                 ("fp16", 4096, 64, "0"), ("fp16", 4096, 64, "1"),
+                                                 ("fp16", 2048, 64, "0"), ("fp16", 2048, 64, "1")])
 def test_noalloc_matches_the_batch_entry_point(gpu, monkeypatch, prec, L, m, persistent):
     monkeypatch.setenv("FDAS_BATCH_PERSISTENT", persistent)
     bar = 1e-4 if prec == "fp32" else 1e-3
