@@ -55,7 +55,8 @@ extern "C" {
 #define FDAS_MIXED_BF16 2  /* BF16 storage, MFMA DFT stages, FP32 accumulate */
 
 /* ---- flags ----------------------------------------------------------------- */
-#define FDAS_FLAG_SPLIT 1u    /* mixed: hi+lo split products (3 MFMA per stage) */
+#define FDAS_FLAG_SPLIT 1u    /* mixed: hi+lo split products (3 MFMA per stage;
+                                 seg_len 4096) */
 #define FDAS_FLAG_AUTOTUNE 2u /* fdas_plan: time the compiled variants (segment
                                  length, radix split, threads, templates per
                                  block) on a synthetic spectrum of 2^20 bins and

@@ -38,6 +38,7 @@ def test_mixed_bank_matches_oracle(gpu, prec):
     ("fp16", 3 * 3840 + 517, 10.0, 256),
     ("fp16", 1000, 6.0, 256),
     ("fp16", 20000, 30.0, 512),
+    ("fp16", 9000, 12.0, 100),     # m/2 = 50: every segment takes the per-value stores
 ])
 def test_mixed_full_plane(gpu, prec, nbins, zmax, m):
     a = synth.small_random_spectrum(nbins, seed=nbins)

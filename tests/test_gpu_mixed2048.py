@@ -41,6 +41,7 @@ def test_bank_matches_oracle(gpu, prec, tol):
     ("fp16", 700, 6.0, 256),                 # less than one segment
     ("fp16", 20000, 30.0, 1024),             # widest filter: half of each segment kept
     ("fp16", 9001, 16.0, 64),
+    ("fp16", 7000, 12.0, 100),               # m/2 = 50: every segment takes the per-value stores
     ("bf16", 3 * 1792 + 517, 10.0, 256),
 ])
 def test_full_plane(gpu, prec, nbins, zmax, m):
