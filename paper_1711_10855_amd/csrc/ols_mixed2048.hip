@@ -15,10 +15,11 @@
 //   S0 (radix 16): for the same n2, rows n1, K = k0, columns n0; its
 //     twiddle w256^(n1 k0) depends on a row and a K index, so it is applied
 //     to S1's results in FP32 (four complex products per lane).
-// S2 has 8 complex inputs and outputs per butterfly: its A operand fills K
-// 0..15 (Re Y over k2, then Im Y) and leaves K 16..31 zero, and one matrix
-// B = [[Re C, Im C], [-Im C, Re C]] gives both parts of the output (columns
-// 0..7 real, 8..15 imaginary).
+// S2 has 8 complex inputs and outputs per butterfly: its A operand holds the
+// four plane-pair products of Y = X T over k2 (Re X Re T, Im X Im T,
+// Re X Im T, Im X Re T: K 0..31), and one matrix combines them into both
+// parts of the output (columns 0..7 real, 8..15 imaginary), so the complex
+// product's sums run in the matrix core's FP32 accumulation.
 //
 // S1 and S0 of one n2 run back to back in one wave: S1 leaves lane (g, c)
 // with rows k0 = 4g .. 4g+3 of column n1 = c, and S0 needs in lane (g, c)
@@ -32,10 +33,11 @@
 //   frequency, exchanging through LDS; X[k0 + 16 k1 + 256 k2] lands in LDS
 //   slot 8 (16 k0 + k1) + k2), per-segment power-of-two scale, X rounded to
 //   16 bits and kept in registers as S2's operand chunks;
-//   per template, with a single barrier: the product and S2 on all 16 waves
-//   into one of two exchange buffers | S1, the twiddle, the exchange and S0
-//   on waves 0..7 (n2 = wave) into one of two staging buffers, while waves
-//   8..15 store the previous template's powers from the other.
+//   per template, with a single barrier and two roles: waves 8..15 form the
+//   products and S2 (two k0 tiles each) into one of two exchange buffers and
+//   load the next bank row; waves 0..7 (n2 = wave) run S1, the twiddle and
+//   the exchange of this template, S0 of the previous one into one of two
+//   staging buffers, and the stores of the one before.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -72,7 +74,7 @@ struct V<__bf16> {
 };
 
 constexpr int L = 2048;
-constexpr int NW = 16;  // waves per block, one tile each per stage
+constexpr int NW = 16;  // waves per block: 8 for S2 (two tiles each), 8 for S1-S0 (one n2 each)
 
 // ---- LDS layout (bytes) ----------------------------------------------------
 // Forward FFT (FP32): A -> B exchange, rows of 128 values padded to 132;
