@@ -101,7 +101,7 @@ int resolve_params(const fdas_params *in, fdas_params *out, int *nz_out) {
 
 int default_seg_len(int m, int nz, int precision) {
   (void)nz;
-  if (precision != FDAS_FP32) return 4096;  // the compiled matrix-core length
+  if (precision != FDAS_FP32) return 4096;  // the faster matrix-core length
   int L = next_pow2(8.0 * m);
   if (L < 256) L = 256;
   if (L > 16384) L = 16384;

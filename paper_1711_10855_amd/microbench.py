@@ -14,7 +14,10 @@ overlap-and-save made of library calls on the same bank: ``torch.fft.fft``
 of every segment, a broadcast product with the bank, ``torch.fft.ifft`` and
 the discard/|.|^2 as torch element-wise kernels, the way a library-based
 convolution is assembled. The library pipeline is a comparator only; its
-plane is checked against the fused kernel's.
+plane is checked against the fused kernel's. Each row also gives the fused
+kernels' plane points/s and their fraction of the HBM roofline, at
+4 + 8/nz algorithmic bytes per point (one FP32 power written, each input bin
+read once).
 
 Front end: ``fdas_frontend_exec`` (real series -> normalised spectrum on the
 device) for series of 2^16 .. 2^24 samples, against the same steps as torch
@@ -38,6 +41,8 @@ if os.path.dirname(HERE) not in sys.path:
     sys.path.insert(0, os.path.dirname(HERE))
 
 from paper_1711_10855_amd import fdas  # noqa: E402
+
+HBM_PEAK = 8.0e12    # MI355X HBM3E peak, bytes/s
 
 
 def _time(fn, reps, warm):
@@ -129,14 +134,20 @@ def table2(emit, filters=(64, 128, 256, 384, 512), nbins=1 << 21, zmax=100.0, dz
             ms_lib = _time(lambda: lib(spec, ref), reps=5, warm=2)
             diff = float((plane - ref).abs().max() / ref.max())
             kern = p.info.kernel
+        pts = nz * nbins
+        bpp = 4.0 + 8.0 / nz    # one FP32 power written per point, each input bin read once
         row = {"table": 2, "m": m, "nz": nz, "nbins": nbins, "seg_len": L, "kernel": kern,
-               "ms": ms, "ms_library_ols": ms_lib, "speedup_vs_library": ms_lib / ms,
+               "ms": ms, "points_per_s": pts / ms * 1e3,
+               "hbm_roofline_frac": pts / ms * 1e3 * bpp / HBM_PEAK,
+               "ms_library_ols": ms_lib, "speedup_vs_library": ms_lib / ms,
                "max_rel_diff_vs_library": diff}
         with fdas.Plan(zmax, dz, m, 0, "fp16") as q:
             plane16 = torch.empty((q.nz, nbins), dtype=torch.float32, device="cuda")
             ms16 = _time(lambda: q.convolve(spec, out=plane16), reps=100, warm=200)
             row.update({"kernel_fp16": q.info.kernel, "seg_len_fp16": q.info.seg_len,
-                        "ms_fp16": ms16, "speedup_fp16_vs_library": ms_lib / ms16})
+                        "ms_fp16": ms16, "points_per_s_fp16": pts / ms16 * 1e3,
+                        "hbm_roofline_frac_fp16": pts / ms16 * 1e3 * bpp / HBM_PEAK,
+                        "speedup_fp16_vs_library": ms_lib / ms16})
         emit(row)
 
 
