@@ -360,7 +360,29 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
   constexpr int BP = SPLIT ? 4 : 2;  // planes per bank row
   const int pu = (re_lane ? 0 : 1) * L, pv = (re_lane ? 1 : 0) * L;
   v8 btr[TPW], bti[TPW], btrl[SPLIT ? TPW : 1], btil[SPLIT ? TPW : 1];
+  // (PF == 5) the same loads through a buffer resource over the bank row (a
+  // wave-uniform base), so the lanes' byte offsets stay fixed and no 64-bit
+  // address is formed per lane and template.
+  const int boff_u = (pu + (16 * (TPW * w) + c) * 16 + 8 * h) * 2;  // tile j adds 512 j
+  const int boff_v = (pv + (16 * (TPW * w) + c) * 16 + 8 * h) * 2;
+  auto load_bank_buf = [&](int iz) {
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<H *>(bank_) + (int64_t)iz * (BP * L), (short)0, BP * L * 2, 0x00020000);
+#pragma unroll
+    for (int j = 0; j < TPW; ++j) {
+      btr[j] = __builtin_bit_cast(v8, __builtin_amdgcn_raw_buffer_load_b128(rs, boff_u + 512 * j, 0, 0));
+      bti[j] = __builtin_bit_cast(v8, __builtin_amdgcn_raw_buffer_load_b128(rs, boff_v + 512 * j, 0, 0));
+      if constexpr (SPLIT) {
+        btrl[j] = __builtin_bit_cast(v8, __builtin_amdgcn_raw_buffer_load_b128(rs, boff_u + 512 * j + 4 * L, 0, 0));
+        btil[j] = __builtin_bit_cast(v8, __builtin_amdgcn_raw_buffer_load_b128(rs, boff_v + 512 * j + 4 * L, 0, 0));
+      }
+    }
+  };
   auto load_bank = [&](int iz) {
+    if constexpr (PF == 5 && !CAND) {
+      load_bank_buf(iz);
+      return;
+    }
     const auto brow = bank + (int64_t)iz * (BP * L);
 #pragma unroll
     for (int j = 0; j < TPW; ++j) {
@@ -393,8 +415,43 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
     for (int q = 0; q < TPW; ++q)
       v[q] = *reinterpret_cast<const f4 *>(stg + 260 * (TPW * w + q) + 4 * lane);
   };
+  // PF == 5 stores through a buffer resource that spans the segment's kept
+  // outputs in plane row izr: every lane issues its 16-byte store, and a lane
+  // whose group is not kept passes an offset past the resource's end, which
+  // the hardware drops. That store is issued on every path (it writes nothing
+  // when `none` is set or the unit takes the per-value stores), so every
+  // path has at least one store after the bank row loaded before it.
+  auto write_staged_buffer = [&](int izr, const f4 *vv, bool none) {
+    const int64_t rbase = (int64_t)s * U;  // plane column of segment output `half`
+    const int64_t left = nbins - rbase;
+    const int nkeep = (int)(left < U ? left : U);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        power_ + (int64_t)(izr - row_base) * ld + rbase, (short)0, nkeep * 4, 0x00020000);
+    constexpr int aux = NT ? 2 : 0;  // nontemporal
+    constexpr int kPast = (int)0x80000000u;
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+      const int o0 = 256 * (TPW * w + q) + 4 * lane;
+      const bool keep4 = !none && vec_ok && o0 >= half && o0 < half + U;
+      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, vv[q]), rs,
+                                             keep4 ? (o0 - half) * 4 : kPast, 0, aux);
+      if (!vec_ok && !none) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int o = o0 + i;
+          const bool keep = !none && o >= half && o < half + U && o - half < nkeep;
+          __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(vv[q][i]), rs,
+                                                keep ? (o - half) * 4 : kPast, 0, aux);
+        }
+      }
+    }
+  };
   auto write_staged = [&](int izr, const f4 *vv) {
     if (!CAND && !active) return;
+    if constexpr (PF == 5 && !CAND) {
+      write_staged_buffer(izr, vv, false);
+      return;
+    }
     const auto prow = power + (int64_t)(izr - row_base) * ld;
 #pragma unroll
     for (int q = 0; q < TPW; ++q) {
@@ -513,7 +570,35 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
   // bank row at the next product, stores of the same template included. On
   // the unsplit forms 2-3% faster than PF == 2 on the wide batch and the
   // paper-scale plane; on the split form 1% slower.
-  if constexpr (PF == 3) {
+  // PF == 5: as PF == 4, with the same vector-memory operations on every
+  // path: each template loads a bank row (the last template its own row
+  // again) and then issues its stores (the first template, which has no
+  // previous powers, a store that writes nothing), and the loop is entered
+  // after one such store. The stores then always follow the bank row they
+  // share the counter with, so the wait for that row at the next product
+  // leaves the newest template's stores outstanding: each store has until the
+  // product after next, not the next one, to complete.
+  if constexpr (PF == 5 && !CAND) {
+    if (z0 < z1 && active) {
+      load_bank(z0);
+      f4 v[TPW];
+#pragma unroll
+      for (int q = 0; q < TPW; ++q) v[q] = __builtin_bit_cast(f4, K.q1[0]);  // any live value: nothing is written
+      write_staged_buffer(z0, v, true);
+      for (int iz = z0; iz < z1; ++iz) {
+        product_stage2();
+        load_bank(iz + 1 < z1 ? iz + 1 : iz);
+        __syncthreads();
+        stage1();
+        read_staged(v);
+        write_staged_buffer(iz > z0 ? iz - 1 : iz, v, iz == z0);
+        __syncthreads();
+        stage0();
+      }
+      __syncthreads();
+      store_staged(z1 - 1);
+    }
+  } else if constexpr (PF == 3) {  // (the detection epilogue of PF == 5 runs the PF == 4 loop below)
     if (z0 < z1) {
       load_bank(z0);
       drain_vm();  // nothing outstanding on loop entry
@@ -547,7 +632,7 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
     for (int iz = z0; iz < z1; ++iz) {
       if (!PF) load_bank(iz);
       product_stage2();
-      if ((PF == 2 || PF == 4) && iz + 1 < z1) load_bank(iz + 1);
+      if ((PF == 2 || PF == 4 || PF == 5) && iz + 1 < z1) load_bank(iz + 1);
       __syncthreads();
       if constexpr (PF == 2) drain_vm();
       stage1();
@@ -751,6 +836,7 @@ static OlsVariant make_mixed(const char *name, int precision) {
 
 static const OlsVariant kMixedVariants[] = {
     // the first of each precision and split form is its default
+    make_mixed<_Float16, 5, true, 16, 8, false>("fp16_L4096_mfma_w16_pfb", 1),
     make_mixed<_Float16, 4, true, 16, 8, false>("fp16_L4096_mfma_w16_pfn", 1),
     make_mixed<_Float16, 2, true, 16, 8, false>("fp16_L4096_mfma_w16_pfw", 1),
     make_mixed<_Float16, 3, true, 16, 8, false>("fp16_L4096_mfma_w16_rot", 1),
@@ -761,7 +847,9 @@ static const OlsVariant kMixedVariants[] = {
     make_mixed<__bf16, 2, true, 16, 8, false>("bf16_L4096_mfma_w16_pfw", 2),
     make_mixed<__bf16, 1, true, 8, 4, false>("bf16_L4096_mfma_w8_pf", 2),
     // hi + lo split products (FDAS_FLAG_SPLIT)
+    make_mixed<_Float16, 5, true, 16, 4, true>("fp16_L4096_mfma_split_w16_pfb", 1),
     make_mixed<_Float16, 2, true, 16, 4, true>("fp16_L4096_mfma_split_w16_pfw", 1),
+    make_mixed<__bf16, 5, true, 16, 4, true>("bf16_L4096_mfma_split_w16_pfb", 2),
     make_mixed<__bf16, 2, true, 16, 4, true>("bf16_L4096_mfma_split_w16_pfw", 2),
     make_mixed<__bf16, 4, true, 16, 4, true>("bf16_L4096_mfma_split_w16_pfn", 2),
     make_mixed<__bf16, 3, true, 16, 4, true>("bf16_L4096_mfma_split_w16_rot", 2),

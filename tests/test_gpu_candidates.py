@@ -52,6 +52,30 @@ def test_candidates_match_oracle(gpu, prec, L, m, flags, tol):
     assert np.max(np.abs(pw - ref_plane[row, r])) <= band
 
 
+def _mixed4096_variants():
+    from paper_1711_10855_amd import fdas
+    return fdas.kernel_variants(4096, "fp16") + fdas.kernel_variants(4096, "bf16")
+
+
+@pytest.mark.parametrize("name", _mixed4096_variants())
+def test_candidates_every_mixed_variant(gpu, name, monkeypatch):
+    """Each 4096-point matrix-core variant's detection epilogue reports
+    exactly the points of that variant's own plane at or above the
+    threshold."""
+    monkeypatch.setenv("FDAS_VARIANT", name)
+    prec = "bf16" if name.startswith("bf16") else "fp16"
+    a = synth.small_random_spectrum(20000, seed=90)
+    a[7000:7010] *= 6.0
+    with gpu.Plan(16.0, 2.0, 64, 4096, prec, gpu.FLAG_SPLIT if "_split" in name else 0) as p:
+        assert p.info.kernel == name
+        rec, cnt = p.candidates(to_dev(a), 9.0, capacity=1 << 16)
+        row, r, pw = gpu.decode_candidates(rec, cnt)
+        plane = p.convolve(to_dev(a)).cpu().numpy()
+    assert int(cnt.cpu()[0]) == row.size > 0
+    assert as_set(row, r) == as_set(*np.nonzero(plane >= 9.0))
+    assert np.array_equal(pw, plane[row, r])
+
+
 def test_candidate_capacity_overflow(gpu):
     a = synth.small_random_spectrum(30000, seed=89)
     with gpu.Plan(16.0, 2.0, 64, 512) as p:

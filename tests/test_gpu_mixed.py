@@ -134,6 +134,47 @@ def test_every_mixed_variant(gpu, name, monkeypatch):
     assert err <= (TOL_MIXED if (prec == "fp16" or split) else 2e-2)
 
 
+@pytest.mark.parametrize("name", _mixed_variants())
+def test_every_mixed_variant_batch(gpu, name, monkeypatch):
+    """Each variant in the persistent batched form, with rows padded to a
+    multiple of 4 (16-byte stores on whole segments, per-value stores on the
+    ragged last one) and untouched padding."""
+    import torch
+    prec = "bf16" if name.startswith("bf16") else "fp16"
+    split = "_split" in name
+    monkeypatch.setenv("FDAS_VARIANT", name)
+    monkeypatch.setenv("FDAS_BATCH_PERSISTENT", "1")
+    specs = [(9000, 16.0), (4100, 0.0), (20000, 10.0)]
+    spectra = [synth.small_random_spectrum(n, seed=700 + k) for k, (n, _) in enumerate(specs)]
+    outs = [torch.full((int(round(z)) + 1, (n + 3) // 4 * 4 + 4), -5.0, dtype=torch.float32,
+                       device="cuda") for n, z in specs]
+    with gpu.Plan(16.0, 2.0, 256, 4096, prec, gpu.FLAG_SPLIT if split else 0) as p:
+        assert p.info.kernel == name
+        p.convolve_batch([to_dev(a) for a in spectra], [z for _, z in specs], outs)
+        res = [o.cpu().numpy() for o in outs]
+    for (n, z), a, o in zip(specs, spectra, res):
+        err = rel_err(o[:, :n], oracle.plane_direct(a, z, 2.0, 256))
+        print(f"{name} batch nbins={n} zmax={z}: {err:.3e}")
+        assert err <= (TOL_MIXED if (prec == "fp16" or split) else 2e-2)
+        assert np.all(o[:, n:] == -5.0)
+
+
+@pytest.mark.parametrize("name", _mixed_variants())
+def test_every_mixed_variant_odd_half(gpu, name, monkeypatch):
+    """m = 100: m / 2 is not a multiple of 4, so every segment stores value by
+    value."""
+    prec = "bf16" if name.startswith("bf16") else "fp16"
+    split = "_split" in name
+    monkeypatch.setenv("FDAS_VARIANT", name)
+    a = synth.small_random_spectrum(9001, seed=37)
+    with gpu.Plan(6.0, 2.0, 100, 4096, prec, gpu.FLAG_SPLIT if split else 0) as p:
+        assert p.info.kernel == name
+        out = p.convolve(to_dev(a)).cpu().numpy()
+    err = rel_err(out, oracle.plane_direct(a, 6.0, 2.0, 100))
+    print(f"{name} m=100: {err:.3e}")
+    assert err <= (TOL_MIXED if (prec == "fp16" or split) else 2e-2)
+
+
 # ---- hi + lo split products (FDAS_FLAG_SPLIT) -------------------------------
 
 @pytest.mark.parametrize("prec,tol", [("fp16", 1e-6), ("bf16", 5e-5)])
