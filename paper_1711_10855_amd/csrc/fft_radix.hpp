@@ -109,28 +109,80 @@ __device__ __forceinline__ void dft8(c32 *v) {
   v[7] = csub(e3, o3);
 }
 
-// v[0..16) natural order in and out: 4 x 4 decomposition n = 4 n1 + n2,
-// k = k1 + 4 k2, internal twiddle W16^(n2 k1).
+// ---- second pass of the 16-point DFT ----------------------------------------
+// After the first radix-4 pass v[4 k1 + n2] holds Y[n2][k1]; the second pass
+// is, for each k1, a radix-4 DFT over n2 of Y[n2][k1] W16^(n2 k1). The
+// twiddles are written as a scale times a cheaper factor,
+//   W^1 = C (1 + D i t),  W^3 = C (t + D i),  W^2 = H (1 + D i),
+//   W^4 = D i,  W^6 = D i W^2,  W^9 = -W^1
+// (D = DIR, C = cos(pi/8), t = tan(pi/8), H = 1/sqrt 2), the cheap factors
+// are applied first (two fused multiply-adds or two adds each), and the
+// scale moves into the butterfly's last adds, which become fused
+// multiply-adds: for a group the two odd twiddles share the scale C and the
+// even ones the scale H. 16 operations fewer than twiddle-then-butterfly.
+
+// v * (1 + D i t) and v * (t + D i)
 template <int DIR>
-__device__ __forceinline__ void dft16(c32 *v) {
-  dft4<DIR>(v[0], v[4], v[8], v[12]);
-  dft4<DIR>(v[1], v[5], v[9], v[13]);
-  dft4<DIR>(v[2], v[6], v[10], v[14]);
-  dft4<DIR>(v[3], v[7], v[11], v[15]);
-  // after the first pass v[4*k1 + n2] holds Y[n2][k1]
-  v[5] = tw16<DIR, 1>(v[5]);
-  v[9] = tw16<DIR, 2>(v[9]);
-  v[13] = tw16<DIR, 3>(v[13]);
-  v[6] = tw16<DIR, 2>(v[6]);
-  v[10] = tw16<DIR, 4>(v[10]);
-  v[14] = tw16<DIR, 6>(v[14]);
-  v[7] = tw16<DIR, 3>(v[7]);
-  v[11] = tw16<DIR, 6>(v[11]);
-  v[15] = tw16<DIR, 9>(v[15]);
-  dft4<DIR>(v[0], v[1], v[2], v[3]);
-  dft4<DIR>(v[4], v[5], v[6], v[7]);
-  dft4<DIR>(v[8], v[9], v[10], v[11]);
-  dft4<DIR>(v[12], v[13], v[14], v[15]);
+__device__ __forceinline__ c32 tw_c1(c32 v) {
+  constexpr float T8 = 0.41421356237309504880f;  // tan(pi/8)
+  return {__builtin_fmaf(-DIR * T8, v.y, v.x), __builtin_fmaf(DIR * T8, v.x, v.y)};
+}
+template <int DIR>
+__device__ __forceinline__ c32 tw_c3(c32 v) {
+  constexpr float T8 = 0.41421356237309504880f;
+  return {__builtin_fmaf(T8, v.x, -DIR * v.y), __builtin_fmaf(T8, v.y, DIR * v.x)};
+}
+// v * (1 + D i)
+template <int DIR>
+__device__ __forceinline__ c32 tw_h(c32 v) {
+  if constexpr (DIR < 0) return {v.x + v.y, v.y - v.x};
+  else return {v.x - v.y, v.y + v.x};
+}
+// a + k b and a - k b for a real scale k
+__device__ __forceinline__ c32 caxpy(c32 a, float k, c32 b) {
+  return {__builtin_fmaf(k, b.x, a.x), __builtin_fmaf(k, b.y, a.y)};
+}
+
+// Radix-4 butterfly over (p0, C a1, p2, C a3) with p2 = H u2 (EVEN_H) or
+// p2 given (EVEN_H false), ODD_SIGN = -1 when the third input is -C a3.
+template <int DIR, bool EVEN_H, int ODD_SIGN>
+__device__ __forceinline__ void bfly_c(c32 &o0, c32 &o1, c32 &o2, c32 &o3, c32 p0, c32 a1, c32 p2,
+                                       c32 a3) {
+  constexpr float C1 = 0.92387953251128675613f;  // cos(pi/8)
+  constexpr float H = 0.70710678118654752440f;
+  const c32 t0 = EVEN_H ? caxpy(p0, H, p2) : cadd(p0, p2);
+  const c32 t1 = EVEN_H ? caxpy(p0, -H, p2) : csub(p0, p2);
+  const c32 s = ODD_SIGN > 0 ? cadd(a1, a3) : csub(a1, a3);   // (p1 + p3) / C
+  const c32 d = rot90<DIR>(ODD_SIGN > 0 ? csub(a1, a3) : cadd(a1, a3));  // D i (p1 - p3) / C
+  o0 = caxpy(t0, C1, s);
+  o2 = caxpy(t0, -C1, s);
+  o1 = caxpy(t1, C1, d);
+  o3 = caxpy(t1, -C1, d);
+}
+
+template <int DIR>
+__device__ __forceinline__ void dft16_pass2(c32 *v) {
+  constexpr float H = 0.70710678118654752440f;
+  dft4<DIR>(v[0], v[1], v[2], v[3]);  // k1 = 0: no twiddles
+  {  // k1 = 1: W^1, W^2, W^3
+    const c32 p0 = v[4], a1 = tw_c1<DIR>(v[5]), u2 = tw_h<DIR>(v[6]), a3 = tw_c3<DIR>(v[7]);
+    bfly_c<DIR, true, +1>(v[4], v[5], v[6], v[7], p0, a1, u2, a3);
+  }
+  {  // k1 = 2: W^2, W^4, W^6 = D i W^2 (all with the scale H or none)
+    const c32 p0 = v[8], p2 = rot90<DIR>(v[10]);
+    const c32 u1 = tw_h<DIR>(v[9]), u3 = rot90<DIR>(tw_h<DIR>(v[11]));
+    const c32 t0 = cadd(p0, p2), t1 = csub(p0, p2);
+    const c32 s = cadd(u1, u3), d = rot90<DIR>(csub(u1, u3));
+    v[8] = caxpy(t0, H, s);
+    v[10] = caxpy(t0, -H, s);
+    v[9] = caxpy(t1, H, d);
+    v[11] = caxpy(t1, -H, d);
+  }
+  {  // k1 = 3: W^3, W^6 = D i W^2, W^9 = -W^1
+    const c32 p0 = v[12], a1 = tw_c3<DIR>(v[13]), u2 = rot90<DIR>(tw_h<DIR>(v[14]));
+    const c32 a3 = tw_c1<DIR>(v[15]);
+    bfly_c<DIR, true, -1>(v[12], v[13], v[14], v[15], p0, a1, u2, a3);
+  }
   // now v[4*k1 + k2] holds X[k1 + 4 k2]; transpose to natural order
   c32 t;
   t = v[1]; v[1] = v[4]; v[4] = t;
@@ -139,6 +191,17 @@ __device__ __forceinline__ void dft16(c32 *v) {
   t = v[6]; v[6] = v[9]; v[9] = t;
   t = v[7]; v[7] = v[13]; v[13] = t;
   t = v[11]; v[11] = v[14]; v[14] = t;
+}
+
+// v[0..16) natural order in and out: 4 x 4 decomposition n = 4 n1 + n2,
+// k = k1 + 4 k2, internal twiddle W16^(n2 k1).
+template <int DIR>
+__device__ __forceinline__ void dft16(c32 *v) {
+  dft4<DIR>(v[0], v[4], v[8], v[12]);
+  dft4<DIR>(v[1], v[5], v[9], v[13]);
+  dft4<DIR>(v[2], v[6], v[10], v[14]);
+  dft4<DIR>(v[3], v[7], v[11], v[15]);
+  dft16_pass2<DIR>(v);
 }
 
 // ---- twiddled butterflies ---------------------------------------------------
@@ -187,26 +250,7 @@ __device__ __forceinline__ void dft16_tw(c32 *v, const c32 *w) {
   dft4_tw<DIR, CONJ, true>(v[1], v[5], v[9], v[13], w[1], w[5], w[9], w[13]);
   dft4_tw<DIR, CONJ, true>(v[2], v[6], v[10], v[14], w[2], w[6], w[10], w[14]);
   dft4_tw<DIR, CONJ, true>(v[3], v[7], v[11], v[15], w[3], w[7], w[11], w[15]);
-  v[5] = tw16<DIR, 1>(v[5]);
-  v[9] = tw16<DIR, 2>(v[9]);
-  v[13] = tw16<DIR, 3>(v[13]);
-  v[6] = tw16<DIR, 2>(v[6]);
-  v[10] = tw16<DIR, 4>(v[10]);
-  v[14] = tw16<DIR, 6>(v[14]);
-  v[7] = tw16<DIR, 3>(v[7]);
-  v[11] = tw16<DIR, 6>(v[11]);
-  v[15] = tw16<DIR, 9>(v[15]);
-  dft4<DIR>(v[0], v[1], v[2], v[3]);
-  dft4<DIR>(v[4], v[5], v[6], v[7]);
-  dft4<DIR>(v[8], v[9], v[10], v[11]);
-  dft4<DIR>(v[12], v[13], v[14], v[15]);
-  c32 t;
-  t = v[1]; v[1] = v[4]; v[4] = t;
-  t = v[2]; v[2] = v[8]; v[8] = t;
-  t = v[3]; v[3] = v[12]; v[12] = t;
-  t = v[6]; v[6] = v[9]; v[9] = t;
-  t = v[7]; v[7] = v[13]; v[13] = t;
-  t = v[11]; v[11] = v[14]; v[14] = t;
+  dft16_pass2<DIR>(v);
 }
 
 template <int DIR, bool CONJ>

@@ -59,11 +59,25 @@ __device__ __forceinline__ void ols_unit(const c32 *__restrict__ spec_, int64_t 
         x[j * R0 + n] = v;
       }
   }
+  // Bank rows are read through a buffer resource over the row (a wave-uniform
+  // base): the lane's byte offset t * 8 in its offset register, the element's
+  // e T * 8 as a scalar offset, so one register serves every element and no
+  // 64-bit address is formed per element and template.
+  auto bank_row = [&](int iz) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<c32 *>(bank_) + (int64_t)iz * L, (short)0,
+                                             L * 8, 0x00020000);
+  };
+  const int boff = t * 8;
+  auto bank_elem = [&](const __amdgpu_buffer_rsrc_t &rs, int e) {
+    const f2v v = __builtin_bit_cast(
+        f2v, __builtin_amdgcn_raw_buffer_load_b64(rs, boff, e * T * 8, 0));
+    return c32{v.x, v.y};
+  };
   c32 bnext[PF ? E : 1];
   if constexpr (PF) {
-    const auto brow = bank + (int64_t)z0 * L + t;
+    const auto rs = bank_row(z0);
 #pragma unroll
-    for (int e = 0; e < E; ++e) bnext[e] = ldg(brow + e * T);
+    for (int e = 0; e < E; ++e) bnext[e] = bank_elem(rs, e);
   }
 
   // forward, decimation in frequency
@@ -100,6 +114,24 @@ __device__ __forceinline__ void ols_unit(const c32 *__restrict__ spec_, int64_t 
     });
   }
 
+  // Byte offsets of the outputs in the store resource (see the stores), one
+  // per output slot, computed once per unit; each passes through an empty
+  // asm statement so that it reaches the store whole in the lane's offset
+  // register (no constant part is moved into the immediate field).
+  constexpr bool kBufStore = !CAND && T >= 64;
+  int soff[kBufStore ? E : 1];
+  if constexpr (kBufStore) {
+    constexpr int S0 = Gm::S(0), R0 = Gm::R[0];
+#pragma unroll
+    for (int j = 0; j < Gm::B(0); ++j)
+#pragma unroll
+      for (int n = 0; n < R0; ++n) {
+        int off = (n * S0 + t + j * T - half) * 4;
+        asm volatile("" : "+v"(off));
+        soff[j * R0 + n] = off;
+      }
+  }
+
   // one template; P0 is the buffer parity at its start
   auto one = [&](int iz, auto p0c) {
     constexpr int P0 = decltype(p0c)::value;
@@ -110,13 +142,13 @@ __device__ __forceinline__ void ols_unit(const c32 *__restrict__ spec_, int64_t 
       // the last template reloads its own row: an unconditional load keeps
       // one register set for the bank (a conditional one makes the compiler
       // copy the prefetched values across the loop edge)
-      const auto brow = bank + (int64_t)(iz + 1 < z1 ? iz + 1 : iz) * L + t;
+      const auto rs = bank_row(iz + 1 < z1 ? iz + 1 : iz);
 #pragma unroll
-      for (int e = 0; e < E; ++e) bnext[e] = ldg(brow + e * T);
+      for (int e = 0; e < E; ++e) bnext[e] = bank_elem(rs, e);
     } else {
-      const auto brow = bank + (int64_t)iz * L + t;
+      const auto rs = bank_row(iz);
 #pragma unroll
-      for (int e = 0; e < E; ++e) y[e] = cmul(x[e], ldg(brow + e * T));
+      for (int e = 0; e < E; ++e) y[e] = cmul(x[e], bank_elem(rs, e));
     }
 
     // inverse, decimation in time: stages P-1 .. 0
@@ -167,7 +199,29 @@ __device__ __forceinline__ void ols_unit(const c32 *__restrict__ spec_, int64_t 
             cand_offer(cd, hit, iz - row_base, r, p);
           }
       }
-    } else if (active) {
+    } else if (kBufStore && active) {
+      // Stores through a buffer resource that starts at plane column s U
+      // (segment output `half`) and spans the segment's kept outputs: output
+      // o goes to byte offset (o - half) * 4, which is negative (so, taken as
+      // unsigned, past the end) for o < half and at or past the end for
+      // o >= half + U or beyond nbins, and the hardware drops those lanes.
+      // (With T >= 64 a wave holds one segment, so s is the same in every
+      // lane and the resource is wave-uniform.)
+      constexpr int S0 = Gm::S(0), R0 = Gm::R[0];
+      const int su = __builtin_amdgcn_readfirstlane(s);
+      const int64_t left = nbins - (int64_t)su * U;
+      const int nkeep = (int)(left < U ? left : U);
+      const auto rs = __builtin_amdgcn_make_buffer_rsrc(
+          power_ + (int64_t)(iz - row_base) * ld + (int64_t)su * U, (short)0, nkeep * 4, 0x00020000);
+#pragma unroll
+      for (int j = 0; j < Gm::B(0); ++j)
+#pragma unroll
+        for (int n = 0; n < R0; ++n) {
+          const c32 v = y[j * R0 + n];
+          __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(__builtin_fmaf(v.x, v.x, v.y * v.y)),
+                                                rs, soff[j * R0 + n], 0, 2 /* nontemporal */);
+        }
+    } else if (active) {  // segments narrower than a wave: per-lane addresses
       constexpr int S0 = Gm::S(0), R0 = Gm::R[0];
       const auto prow = power + (int64_t)(iz - row_base) * ld;
 #pragma unroll
@@ -411,8 +465,8 @@ static const OlsVariant kFp32Variants[] = {
     make_variant<Geo<2048, 128, 8, 16, 16>, 1, false, true, 2>("fp32_L2048_t128_r8.16.16_tg_o2"),
     make_variant<Geo<2048, 256, 4, 8, 8, 8>, 1, true, true, 3>("fp32_L2048_t256_r4.8.8.8"),
     make_variant<Geo<2048, 256, 4, 8, 8, 8>, 1, false, true, 3>("fp32_L2048_t256_r4.8.8.8_tg"),
-    make_variant<Geo<4096, 256, 16, 16, 16>, 1, true, false, 2>("fp32_L4096_t256_r16.16.16_np"),
     make_variant<Geo<4096, 256, 16, 16, 16>, 1, true, true, 2>("fp32_L4096_t256_r16.16.16_o2"),
+    make_variant<Geo<4096, 256, 16, 16, 16>, 1, true, false, 2>("fp32_L4096_t256_r16.16.16_np"),
     make_variant<Geo<4096, 256, 16, 16, 16>, 1, false, true, 2>("fp32_L4096_t256_r16.16.16_tg_o2"),
     make_variant<Geo<4096, 512, 8, 8, 8, 8>, 1, false, true>("fp32_L4096_t512_r8.8.8.8_tg"),
     make_variant<Geo<4096, 512, 8, 8, 8, 8>, 1, true, true, 2>("fp32_L4096_t512_r8.8.8.8_o2"),

@@ -109,6 +109,28 @@ def test_every_variant_full_plane(gpu, variant_env, L, name):
     assert err <= TOL_FP32
 
 
+@pytest.mark.parametrize("L,name", _variants())
+def test_every_variant_padded_rows_odd_half(gpu, variant_env, L, name):
+    """Rows padded by 5 values (row starts not 16-byte aligned), m / 2 odd, a
+    ragged last segment: every output lands where the oracle puts it and the
+    padding stays untouched."""
+    import torch
+    m = max(34, L // 8) | 2          # m / 2 odd
+    nbins = 2 * (L - m) + 333
+    a = synth.small_random_spectrum(nbins, seed=L + 1)
+    ref = oracle.plane_direct(a, 4.0, 2.0, m)
+    variant_env(name)
+    with gpu.Plan(4.0, 2.0, m, L) as p:
+        assert p.info.kernel == name
+        buf = torch.full((p.nz, nbins + 5), -7.0, dtype=torch.float32, device="cuda")
+        p.convolve(to_dev(a), out=buf)
+        b = buf.cpu().numpy()
+    assert np.all(b[:, nbins:] == -7.0)
+    err = rel_err(b[:, :nbins], ref)
+    print(f"{name} m={m} padded: {err:.3e}")
+    assert err <= TOL_FP32
+
+
 @pytest.mark.parametrize("nbins", [1, 2, 31, 191, 192, 193, 384, 1000])
 def test_edge_lengths(gpu, nbins):
     # U = 192 for L = 256, m = 64: below, at and just past segment boundaries
