@@ -243,22 +243,24 @@ __device__ __forceinline__ void dft4_tw(c32 &a, c32 &b, c32 &c, c32 &d, c32 wa, 
   d = csub(t1, t3);
 }
 
-template <int DIR, bool CONJ>
+// W0: the first input carries a factor w[0] too (a radix DFT of a pointwise
+// product v * w), else w[0] = 1 is implied.
+template <int DIR, bool CONJ, bool W0 = false>
 __device__ __forceinline__ void dft16_tw(c32 *v, const c32 *w) {
   const c32 one = {1.f, 0.f};
-  dft4_tw<DIR, CONJ, false>(v[0], v[4], v[8], v[12], one, w[4], w[8], w[12]);
+  dft4_tw<DIR, CONJ, W0>(v[0], v[4], v[8], v[12], W0 ? w[0] : one, w[4], w[8], w[12]);
   dft4_tw<DIR, CONJ, true>(v[1], v[5], v[9], v[13], w[1], w[5], w[9], w[13]);
   dft4_tw<DIR, CONJ, true>(v[2], v[6], v[10], v[14], w[2], w[6], w[10], w[14]);
   dft4_tw<DIR, CONJ, true>(v[3], v[7], v[11], v[15], w[3], w[7], w[11], w[15]);
   dft16_pass2<DIR>(v);
 }
 
-template <int DIR, bool CONJ>
+template <int DIR, bool CONJ, bool W0 = false>
 __device__ __forceinline__ void dft8_tw(c32 *v, const c32 *w) {
   const c32 one = {1.f, 0.f};
   c32 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
   c32 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
-  dft4_tw<DIR, CONJ, false>(e0, e1, e2, e3, one, w[2], w[4], w[6]);
+  dft4_tw<DIR, CONJ, W0>(e0, e1, e2, e3, W0 ? w[0] : one, w[2], w[4], w[6]);
   dft4_tw<DIR, CONJ, true>(o0, o1, o2, o3, w[1], w[3], w[5], w[7]);
   o1 = tw16<DIR, 2>(o1);
   o2 = tw16<DIR, 4>(o2);
@@ -273,19 +275,20 @@ __device__ __forceinline__ void dft8_tw(c32 *v, const c32 *w) {
   v[7] = csub(e3, o3);
 }
 
-template <int DIR, bool CONJ, int R>
+template <int DIR, bool CONJ, int R, bool W0 = false>
 __device__ __forceinline__ void dft_tw(c32 *v, const c32 *w) {
   static_assert(R == 2 || R == 4 || R == 8 || R == 16, "radix");
   if constexpr (R == 2) {
-    const c32 t0 = cfma<CONJ>(v[0], v[1], w[1]);
-    v[1] = twice_minus(v[0], t0);
+    const c32 a = W0 ? cmul_t<CONJ>(v[0], w[0]) : v[0];
+    const c32 t0 = cfma<CONJ>(a, v[1], w[1]);
+    v[1] = twice_minus(a, t0);
     v[0] = t0;
   } else if constexpr (R == 4) {
-    dft4_tw<DIR, CONJ, false>(v[0], v[1], v[2], v[3], c32{1.f, 0.f}, w[1], w[2], w[3]);
+    dft4_tw<DIR, CONJ, W0>(v[0], v[1], v[2], v[3], W0 ? w[0] : c32{1.f, 0.f}, w[1], w[2], w[3]);
   } else if constexpr (R == 8) {
-    dft8_tw<DIR, CONJ>(v, w);
+    dft8_tw<DIR, CONJ, W0>(v, w);
   } else {
-    dft16_tw<DIR, CONJ>(v, w);
+    dft16_tw<DIR, CONJ, W0>(v, w);
   }
 }
 

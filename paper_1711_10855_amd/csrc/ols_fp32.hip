@@ -135,10 +135,16 @@ __device__ __forceinline__ void ols_unit(const c32 *__restrict__ spec_, int64_t 
   // one template; P0 is the buffer parity at its start
   auto one = [&](int iz, auto p0c) {
     constexpr int P0 = decltype(p0c)::value;
-    c32 y[E];
+    // The product Y = X T goes into the first inverse stage's butterflies:
+    // its first layer forms x_a T_a + x_c T_c with fused multiply-adds (as it
+    // would apply twiddles), two operations fewer per pair than multiplying
+    // first.
+    c32 y[E], bt[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) y[e] = x[e];
     if constexpr (PF) {
 #pragma unroll
-      for (int e = 0; e < E; ++e) y[e] = cmul(x[e], bnext[e]);
+      for (int e = 0; e < E; ++e) bt[e] = bnext[e];
       // the last template reloads its own row: an unconditional load keeps
       // one register set for the bank (a conditional one makes the compiler
       // copy the prefetched values across the loop edge)
@@ -148,14 +154,17 @@ __device__ __forceinline__ void ols_unit(const c32 *__restrict__ spec_, int64_t 
     } else {
       const auto rs = bank_row(iz);
 #pragma unroll
-      for (int e = 0; e < E; ++e) y[e] = cmul(x[e], bank_elem(rs, e));
+      for (int e = 0; e < E; ++e) bt[e] = bank_elem(rs, e);
     }
 
     // inverse, decimation in time: stages P-1 .. 0
     static_for_down<P - 1, 0>([&](auto ic) {
       constexpr int I = decltype(ic)::value;
       constexpr int R = Gm::R[I];
-      if constexpr (I < P - 1) {
+      if constexpr (I == P - 1) {
+#pragma unroll
+        for (int j = 0; j < Gm::B(I); ++j) dft_tw<+1, false, R, true>(&y[j * R], &bt[j * R]);
+      } else {
         exchange<Gm, I + 1, I, (P0 + flips<Gm>(I + 1, P - 1)) & 1>(y, buf0, buf1, t);
         constexpr int N = R * Gm::S(I);
 #pragma unroll
@@ -167,9 +176,6 @@ __device__ __forceinline__ void ols_unit(const c32 *__restrict__ spec_, int64_t 
             w[k] = TWREG ? itw[Gm::TWOFF(I) + j * (R - 1) + k - 1] : ldg(tw + (k * mi) * (L / N));
           dft_tw<+1, true, R>(&y[j * R], w);  // conj twiddles folded into the butterfly
         }
-      } else {
-#pragma unroll
-        for (int j = 0; j < Gm::B(I); ++j) dft<+1, R>(&y[j * R]);
       }
     });
 
