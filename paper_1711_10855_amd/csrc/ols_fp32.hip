@@ -463,8 +463,8 @@ static const OlsVariant kFp32Variants[] = {
     make_variant<Geo<256, 16, 16, 16>, 4, true, true>("fp32_L256_t16x4_r16.16"),
     make_variant<Geo<512, 64, 8, 8, 8>, 1, true, true, 4>("fp32_L512_t64_r8.8.8"),
     make_variant<Geo<512, 32, 2, 16, 16>, 2, false, true>("fp32_L512_t32x2_r2.16.16_tg"),
-    make_variant<Geo<1024, 64, 4, 16, 16>, 1, false, true>("fp32_L1024_t64_r4.16.16_tg"),
     make_variant<Geo<1024, 128, 2, 8, 8, 8>, 1, true, true, 4>("fp32_L1024_t128_r2.8.8.8"),
+    make_variant<Geo<1024, 64, 4, 16, 16>, 1, false, true>("fp32_L1024_t64_r4.16.16_tg"),
     make_variant<Geo<1024, 128, 2, 8, 8, 8>, 1, true, true, 3>("fp32_L1024_t128_r2.8.8.8_o3"),
     make_variant<Geo<2048, 128, 8, 16, 16>, 1, true, true, 2>("fp32_L2048_t128_r8.16.16_o2"),
     make_variant<Geo<2048, 128, 8, 16, 16>, 1, true, false>("fp32_L2048_t128_r8.16.16_np"),
