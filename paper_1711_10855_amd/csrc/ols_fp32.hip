@@ -29,6 +29,16 @@
 
 namespace fdas {
 
+// A pointer that is the same in every lane, moved to scalar registers (a
+// buffer resource built from it then needs no per-lane loop).
+template <class T>
+__device__ __forceinline__ T *uniform_ptr(T *p) {
+  const uint64_t a = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+  return reinterpret_cast<T *>(((uint64_t)hi << 32) | lo);
+}
+
 // One work unit: segment s of a spectrum, bank rows [z0, z1), plane rows
 // (iz - row_base). The unit starts on LDS buffer 0: its caller guarantees a
 // block barrier since any earlier unit's last LDS read.
@@ -64,8 +74,8 @@ __device__ __forceinline__ void ols_unit(const c32 *__restrict__ spec_, int64_t 
   // e T * 8 as a scalar offset, so one register serves every element and no
   // 64-bit address is formed per element and template.
   auto bank_row = [&](int iz) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<c32 *>(bank_) + (int64_t)iz * L, (short)0,
-                                             L * 8, 0x00020000);
+    return __builtin_amdgcn_make_buffer_rsrc(uniform_ptr(const_cast<c32 *>(bank_) + (int64_t)iz * L),
+                                             (short)0, L * 8, 0x00020000);
   };
   const int boff = t * 8;
   auto bank_elem = [&](const __amdgpu_buffer_rsrc_t &rs, int e) {
@@ -73,6 +83,7 @@ __device__ __forceinline__ void ols_unit(const c32 *__restrict__ spec_, int64_t 
         f2v, __builtin_amdgcn_raw_buffer_load_b64(rs, boff, e * T * 8, 0));
     return c32{v.x, v.y};
   };
+
   c32 bnext[PF ? E : 1];
   if constexpr (PF) {
     const auto rs = bank_row(z0);
@@ -138,7 +149,8 @@ __device__ __forceinline__ void ols_unit(const c32 *__restrict__ spec_, int64_t 
     // The product Y = X T goes into the first inverse stage's butterflies:
     // its first layer forms x_a T_a + x_c T_c with fused multiply-adds (as it
     // would apply twiddles), two operations fewer per pair than multiplying
-    // first.
+    // first. (The detection epilogue computes the same way, so that its
+    // powers equal the plane's bit for bit.)
     c32 y[E], bt[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) y[e] = x[e];
@@ -218,7 +230,8 @@ __device__ __forceinline__ void ols_unit(const c32 *__restrict__ spec_, int64_t 
       const int64_t left = nbins - (int64_t)su * U;
       const int nkeep = (int)(left < U ? left : U);
       const auto rs = __builtin_amdgcn_make_buffer_rsrc(
-          power_ + (int64_t)(iz - row_base) * ld + (int64_t)su * U, (short)0, nkeep * 4, 0x00020000);
+          uniform_ptr(power_ + (int64_t)(iz - row_base) * ld + (int64_t)su * U), (short)0, nkeep * 4,
+          0x00020000);
 #pragma unroll
       for (int j = 0; j < Gm::B(0); ++j)
 #pragma unroll
