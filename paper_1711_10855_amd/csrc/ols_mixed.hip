@@ -356,25 +356,36 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
     }
   }
 
-  // Bank planes Re, Im (SPLIT: their residuals 2 planes further).
-  constexpr int BP = SPLIT ? 4 : 2;  // planes per bank row
+  // Bank planes Re, Im: 16-bit, or with SPLIT in FP32 (the product is formed
+  // in FP32 there), in the same slot order. A lane takes the 8 values of its
+  // chunk from plane u (Re on lanes g < 2, else Im) and plane v (the other).
+  constexpr int RB = 2 * L * (SPLIT ? 4 : 2);  // bytes per bank row
   const int pu = (re_lane ? 0 : 1) * L, pv = (re_lane ? 1 : 0) * L;
-  v8 btr[TPW], bti[TPW], btrl[SPLIT ? TPW : 1], btil[SPLIT ? TPW : 1];
+  v8 btr[SPLIT ? 1 : TPW], bti[SPLIT ? 1 : TPW];
+  f4 sbr[SPLIT ? 2 * TPW : 1], sbi[SPLIT ? 2 * TPW : 1];  // (SPLIT) values 4q .. 4q+3 of tile j in [2j + q]
   // (PF == 5) the same loads through a buffer resource over the bank row (a
   // wave-uniform base), so the lanes' byte offsets stay fixed and no 64-bit
-  // address is formed per lane and template.
-  const int boff_u = (pu + (16 * (TPW * w) + c) * 16 + 8 * h) * 2;  // tile j adds 512 j
-  const int boff_v = (pv + (16 * (TPW * w) + c) * 16 + 8 * h) * 2;
+  // address is formed per lane and template. Tile j adds 256 j values.
+  constexpr int EB = SPLIT ? 4 : 2;  // bytes per bank value
+  const int boff_u = (pu + (16 * (TPW * w) + c) * 16 + 8 * h) * EB;
+  const int boff_v = (pv + (16 * (TPW * w) + c) * 16 + 8 * h) * EB;
   auto load_bank_buf = [&](int iz) {
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<H *>(bank_) + (int64_t)iz * (BP * L), (short)0, BP * L * 2, 0x00020000);
+        const_cast<unsigned char *>(reinterpret_cast<const unsigned char *>(bank_)) + (int64_t)iz * RB,
+        (short)0, RB, 0x00020000);
 #pragma unroll
     for (int j = 0; j < TPW; ++j) {
-      btr[j] = __builtin_bit_cast(v8, __builtin_amdgcn_raw_buffer_load_b128(rs, boff_u + 512 * j, 0, 0));
-      bti[j] = __builtin_bit_cast(v8, __builtin_amdgcn_raw_buffer_load_b128(rs, boff_v + 512 * j, 0, 0));
       if constexpr (SPLIT) {
-        btrl[j] = __builtin_bit_cast(v8, __builtin_amdgcn_raw_buffer_load_b128(rs, boff_u + 512 * j + 4 * L, 0, 0));
-        btil[j] = __builtin_bit_cast(v8, __builtin_amdgcn_raw_buffer_load_b128(rs, boff_v + 512 * j + 4 * L, 0, 0));
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          sbr[2 * j + q] = __builtin_bit_cast(
+              f4, __builtin_amdgcn_raw_buffer_load_b128(rs, boff_u + 1024 * j + 16 * q, 0, 0));
+          sbi[2 * j + q] = __builtin_bit_cast(
+              f4, __builtin_amdgcn_raw_buffer_load_b128(rs, boff_v + 1024 * j + 16 * q, 0, 0));
+        }
+      } else {
+        btr[j] = __builtin_bit_cast(v8, __builtin_amdgcn_raw_buffer_load_b128(rs, boff_u + 512 * j, 0, 0));
+        bti[j] = __builtin_bit_cast(v8, __builtin_amdgcn_raw_buffer_load_b128(rs, boff_v + 512 * j, 0, 0));
       }
     }
   };
@@ -383,15 +394,20 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
       load_bank_buf(iz);
       return;
     }
-    const auto brow = bank + (int64_t)iz * (BP * L);
 #pragma unroll
     for (int j = 0; j < TPW; ++j) {
       const int row = 16 * (TPW * w + j) + c;
-      btr[j] = *reinterpret_cast<gptr<const v8>>(brow + pu + row * 16 + 8 * h);
-      bti[j] = *reinterpret_cast<gptr<const v8>>(brow + pv + row * 16 + 8 * h);
       if constexpr (SPLIT) {
-        btrl[j] = *reinterpret_cast<gptr<const v8>>(brow + 2 * L + pu + row * 16 + 8 * h);
-        btil[j] = *reinterpret_cast<gptr<const v8>>(brow + 2 * L + pv + row * 16 + 8 * h);
+        const auto frow = reinterpret_cast<gptr<const float>>(bank) + (int64_t)iz * (2 * L);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          sbr[2 * j + q] = *reinterpret_cast<gptr<const f4>>(frow + pu + row * 16 + 8 * h + 4 * q);
+          sbi[2 * j + q] = *reinterpret_cast<gptr<const f4>>(frow + pv + row * 16 + 8 * h + 4 * q);
+        }
+      } else {
+        const auto brow = bank + (int64_t)iz * (2 * L);
+        btr[j] = *reinterpret_cast<gptr<const v8>>(brow + pu + row * 16 + 8 * h);
+        bti[j] = *reinterpret_cast<gptr<const v8>>(brow + pv + row * 16 + 8 * h);
       }
     }
   };
@@ -496,11 +512,11 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
 #pragma unroll
     for (int j = 0; j < TPW; ++j) {
       if constexpr (SPLIT) {
-        // Y = X T in FP32 from X (FP32) and T = hi + lo, then Y = hi + lo
+        // Y = X T in FP32 from X and T (both FP32), then Y = hi + lo
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-          const float tr = (float)btr[j][i] + (float)btrl[j][i];
-          const float ti = (float)bti[j][i] + (float)btil[j][i];
+          const float tr = sbr[2 * j + (i >> 2)][i & 3];
+          const float ti = sbi[2 * j + (i >> 2)][i & 3];
           const float y = __builtin_fmaf(xrf[j][i], tr, xif[j][i] * ti);
           av[j][i] = (H)y;
           avl[j][i] = (H)(y - (float)av[j][i]);
@@ -870,13 +886,14 @@ const OlsVariant *mixed_variants(int *count) {
   return all.data();
 }
 
-// ---- plan-time: 16-bit planar bank in the X layout ------------------------
+// ---- plan-time: planar bank in the X layout --------------------------------
 // bank[i][plane][row*16 + slot] with row = 16 k0 + k1 for frequency
 // k = k0 + 16 k1 + 256 k2 and slot = k2, its two 4-value halves swapped
 // when bit 7 of the row is set (the order in which the kernel reads X);
 // value conj(FFT_L(h_i))[k] (no 1/L; the kernel removes the factor
-// 2^bank_log2 = L from the power). Planes: Re, Im (rounded to 16 bits);
-// with split, two more planes hold the residuals v - round16(v).
+// 2^bank_log2 = L from the power). Planes: Re, Im, rounded to 16 bits, or
+// with split to FP32 (the split kernel forms the product in FP32 and splits
+// it; the same 8 bytes per value as 16-bit hi and lo planes).
 struct c64m {
   double x, y;
 };
@@ -914,10 +931,15 @@ __global__ void bank_mixed_kernel(H *__restrict__ bank, const c64m *__restrict__
     sr += v.x * cs - v.y * sn;
     si += v.x * sn + v.y * cs;
   }
-  H *row_i = bank + (long)i * (split ? 4 : 2) * L;
-  H *lo = split ? row_i + 2 * L : nullptr;
-  put_split(row_i + slot, lo ? lo + slot : nullptr, sr);            // Re T'
-  put_split(row_i + L + slot, lo ? lo + L + slot : nullptr, -si);   // Im T'
+  if (split) {
+    float *row_f = reinterpret_cast<float *>(bank) + (long)i * 2 * L;
+    row_f[slot] = (float)sr;       // Re T'
+    row_f[L + slot] = (float)-si;  // Im T'
+    return;
+  }
+  H *row_i = bank + (long)i * 2 * L;
+  row_i[slot] = (H)sr;       // Re T'
+  row_i[L + slot] = (H)-si;  // Im T'
 }
 
 template <class H>
@@ -928,11 +950,15 @@ __global__ void bank_mixed_natural_kernel(c32 *__restrict__ dst, const H *__rest
   const int i = (int)(idx / L);
   const int slot = (int)(idx % L);
   const int k = bank_slot_k(slot);
-  const H *row_i = bank + (long)i * (split ? 4 : 2) * L;
-  float re = (float)row_i[slot], im = (float)row_i[L + slot];
+  float re, im;
   if (split) {
-    re += (float)row_i[2 * L + slot];
-    im += (float)row_i[3 * L + slot];
+    const float *row_f = reinterpret_cast<const float *>(bank) + (long)i * 2 * L;
+    re = row_f[slot];
+    im = row_f[L + slot];
+  } else {
+    const H *row_i = bank + (long)i * 2 * L;
+    re = (float)row_i[slot];
+    im = (float)row_i[L + slot];
   }
   const float inv = 1.0f / (float)L;
   dst[(long)i * L + k] = {re * inv, im * inv};
