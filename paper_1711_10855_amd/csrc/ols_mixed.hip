@@ -101,6 +101,28 @@ __device__ __forceinline__ int lds_chunk(int row, int h) {
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
+// Two values a, b as 16-bit pairs hi = (round16(a), round16(b)) and
+// lo = (round16(a - hi_a), round16(b - hi_b)). For BF16 the rounded values
+// come back to FP32 from the packed pair itself (a BF16 value is the upper
+// half of an FP32 one): one shift and one mask instead of two conversions.
+// Returns {hi, lo}.
+template <class H>
+__device__ __forceinline__ u32x2 split2(float a, float b) {
+  typedef H h2 __attribute__((ext_vector_type(2)));
+  const h2 ph = {(H)a, (H)b};
+  const unsigned hi = __builtin_bit_cast(unsigned, ph);
+  float ra, rb;
+  if constexpr (std::is_same<H, __bf16>::value) {
+    ra = __uint_as_float(hi << 16);
+    rb = __uint_as_float(hi & 0xffff0000u);
+  } else {
+    ra = (float)ph[0];
+    rb = (float)ph[1];
+  }
+  const h2 pl = {(H)(a - ra), (H)(b - rb)};
+  return {hi, __builtin_bit_cast(unsigned, pl)};
+}
+
 // A lane holds four consecutive values (4g .. 4g+3 of row `row` of the next
 // stage) of both planes; each plane's four go out as one 8-byte write. With
 // SPLIT the buffer has four planes (re hi, im hi, re lo, im lo): each value
@@ -109,20 +131,21 @@ template <class H, bool SPLIT>
 __device__ __forceinline__ void store_stage(H *buf, int row, int g, const f4 &re,
                                             const f4 &im) {
   typedef typename Vec<H>::v4 v4;
-  const v4 rh = {(H)re[0], (H)re[1], (H)re[2], (H)re[3]};
-  const v4 ih = {(H)im[0], (H)im[1], (H)im[2], (H)im[3]};
   const int o = lds_idx(row, 4 * g);
-  *reinterpret_cast<v4 *>(buf + o) = rh;
-  *reinterpret_cast<v4 *>(buf + kPlane + o) = ih;
   if constexpr (SPLIT) {
-    v4 rl, il;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      rl[i] = (H)(re[i] - (float)rh[i]);
-      il[i] = (H)(im[i] - (float)ih[i]);
-    }
-    *reinterpret_cast<v4 *>(buf + 2 * kPlane + o) = rl;
-    *reinterpret_cast<v4 *>(buf + 3 * kPlane + o) = il;
+    const u32x2 r0 = split2<H>(re[0], re[1]), r1 = split2<H>(re[2], re[3]);
+    const u32x2 i0 = split2<H>(im[0], im[1]), i1 = split2<H>(im[2], im[3]);
+    const u32x2 rh = {r0[0], r1[0]}, rl = {r0[1], r1[1]};
+    const u32x2 ih = {i0[0], i1[0]}, il = {i0[1], i1[1]};
+    *reinterpret_cast<u32x2 *>(buf + o) = rh;
+    *reinterpret_cast<u32x2 *>(buf + kPlane + o) = ih;
+    *reinterpret_cast<u32x2 *>(buf + 2 * kPlane + o) = rl;
+    *reinterpret_cast<u32x2 *>(buf + 3 * kPlane + o) = il;
+  } else {
+    const v4 rh = {(H)re[0], (H)re[1], (H)re[2], (H)re[3]};
+    const v4 ih = {(H)im[0], (H)im[1], (H)im[2], (H)im[3]};
+    *reinterpret_cast<v4 *>(buf + o) = rh;
+    *reinterpret_cast<v4 *>(buf + kPlane + o) = ih;
   }
 }
 
@@ -513,14 +536,22 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
     for (int j = 0; j < TPW; ++j) {
       if constexpr (SPLIT) {
         // Y = X T in FP32 from X and T (both FP32), then Y = hi + lo
+        float y[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
           const float tr = sbr[2 * j + (i >> 2)][i & 3];
           const float ti = sbi[2 * j + (i >> 2)][i & 3];
-          const float y = __builtin_fmaf(xrf[j][i], tr, xif[j][i] * ti);
-          av[j][i] = (H)y;
-          avl[j][i] = (H)(y - (float)av[j][i]);
+          y[i] = __builtin_fmaf(xrf[j][i], tr, xif[j][i] * ti);
         }
+        u32x4 hi, lo;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const u32x2 p = split2<H>(y[2 * q], y[2 * q + 1]);
+          hi[q] = p[0];
+          lo[q] = p[1];
+        }
+        av[j] = __builtin_bit_cast(v8, hi);
+        avl[j] = __builtin_bit_cast(v8, lo);
       } else {
         av[j] = xr[j] * btr[j] + xi[j] * bti[j];
       }
