@@ -688,7 +688,7 @@ def bench_single(args, forms, line):
 def main(argv=None):
     args = parse(argv)
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "the correlation runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     if args.variant:
