@@ -44,6 +44,7 @@
 #include <vector>
 
 #include "fft_radix.hpp"
+#include "cand4.hpp"
 #include "ols_variants.hpp"
 
 namespace fdas {
@@ -501,12 +502,7 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
       if constexpr (CAND) {  // detection epilogue instead of the plane (all lanes offer)
         const bool any = v[0] >= cd.thr || v[1] >= cd.thr || v[2] >= cd.thr || v[3] >= cd.thr;
         if (__builtin_amdgcn_ballot_w64(active && any) == 0ull) continue;  // no hit in the wave
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int o = o0 + i;
-          const bool hit = active && o >= half && o < half + U && r0 + i < nbins && v[i] >= cd.thr;
-          cand_offer(cd, hit, izr - row_base, r0 + i, v[i]);
-        }
+        offer4(cd, v, active, o0, half, U, r0, nbins, izr - row_base);
         continue;
       }
       if (vec_ok) {

@@ -43,6 +43,7 @@
 #include <cstdint>
 
 #include "fft_radix.hpp"
+#include "cand4.hpp"
 #include "ols_variants.hpp"
 
 namespace fdas {
@@ -309,10 +310,21 @@ __device__ __forceinline__ void unit2048(const unsigned char *__restrict__ const
   const int n2 = w;
   const v8 bp1 = consts[kPOff + (n2 * 64 + lane) * 2];
   const v8 bp2 = consts[kPOff + (n2 * 64 + lane) * 2 + 1];
-  const v8 bf1 = consts[kFOff + lane * 2];
-  const v8 bf2 = consts[kFOff + lane * 2 + 1];
-  const f4 twr = *to_global(reinterpret_cast<const f4 *>(consts_ + kTwOff) + lane * 2);
-  const f4 twi = *to_global(reinterpret_cast<const f4 *>(consts_ + kTwOff) + lane * 2 + 1);
+  // S0's matrix and the lane's twiddles: held in registers, or in the
+  // detection form, whose offers need registers of their own, read again
+  // from the table at each use (through a pointer the compiler cannot hoist
+  // the loads out of the loop with; these waves issue no other loads, so
+  // the waits are short).
+  const v8 bf1_r = consts[kFOff + lane * 2];
+  const v8 bf2_r = consts[kFOff + lane * 2 + 1];
+  const f4 twr_r = *to_global(reinterpret_cast<const f4 *>(consts_ + kTwOff) + lane * 2);
+  const f4 twi_r = *to_global(reinterpret_cast<const f4 *>(consts_ + kTwOff) + lane * 2 + 1);
+  auto cvec = [&](int i) {  // entry i of the table, as v8
+    return to_global(reinterpret_cast<const v8 *>(opaque_ptr(consts_)))[i];
+  };
+  auto cf4 = [&](int i) {  // f4 entry i past the twiddle offset
+    return to_global(reinterpret_cast<const f4 *>(opaque_ptr(consts_) + kTwOff))[i];
+  };
 
   // Stores: wave w writes outputs [256 w, 256 w + 256), a lane four
   // consecutive ones (1 KB per store instruction), gathered from the
@@ -336,12 +348,7 @@ __device__ __forceinline__ void unit2048(const unsigned char *__restrict__ const
     if constexpr (CAND) {
       const bool any = v[0] >= cd.thr || v[1] >= cd.thr || v[2] >= cd.thr || v[3] >= cd.thr;
       if (__builtin_amdgcn_ballot_w64(active && any) == 0ull) return;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int o = o0 + i;
-        const bool hit = active && o >= half && o < half + U && r0 + i < nbins && v[i] >= cd.thr;
-        cand_offer(cd, hit, izr - row_base, r0 + i, v[i]);
-      }
+      offer4(cd, v, active, o0, half, U, r0, nbins, izr - row_base);
       return;
     }
     const auto dst = prow + r0;
@@ -362,6 +369,8 @@ __device__ __forceinline__ void unit2048(const unsigned char *__restrict__ const
 
   // S1, the twiddle and the exchange from exchange buffer b: S0's operand.
   auto stage1 = [&](int b) {
+    const f4 twr = twr_r;
+    const f4 twi = twi_r;
     const v8 a =
         *reinterpret_cast<const v8 *>(Ea + b * kEaHalves + ea_chunk(g >> 1, n2, c, g & 1));
     const f4 dr = V<H>::mfma(a, bp1, zero);
@@ -395,6 +404,8 @@ __device__ __forceinline__ void unit2048(const unsigned char *__restrict__ const
   };
   // S0 and |.|^2 into staging buffer b: rows n1 = 4g + i, column n0 = c.
   auto stage0 = [&](const v8 &a0, int b) {
+    const v8 bf1 = bf1_r;
+    const v8 bf2 = bf2_r;
     const f4 er = V<H>::mfma(a0, bf1, zero);
     const f4 ei = V<H>::mfma(a0, bf2, zero);
     f4 pw;

@@ -28,8 +28,9 @@ ROOT = os.path.dirname(HERE)
 # while the sources of its own kernel are unchanged.
 FP32_SOURCES = ["csrc/ols_fp32.hip", "csrc/fft_radix.hpp", "csrc/fft_block.hpp",
                 "csrc/layout.hpp", "csrc/ols_variants.hpp"]
-MIXED_SOURCES = ["csrc/ols_mixed.hip", "csrc/fft_radix.hpp", "csrc/ols_variants.hpp"]
-MIXED2048_SOURCES = ["csrc/ols_mixed2048.hip", "csrc/fft_radix.hpp", "csrc/ols_variants.hpp"]
+MIXED_SOURCES = ["csrc/ols_mixed.hip", "csrc/fft_radix.hpp", "csrc/ols_variants.hpp", "csrc/cand4.hpp"]
+MIXED2048_SOURCES = ["csrc/ols_mixed2048.hip", "csrc/fft_radix.hpp", "csrc/ols_variants.hpp",
+                     "csrc/cand4.hpp"]
 
 
 def kernel_sources(kernel: str) -> list[str]:
