@@ -171,8 +171,9 @@ int fdas_plan(fdas_plan_t *out, const fdas_params *p, int device, void *stream);
 int fdas_plan_get_info(fdas_plan_t plan, fdas_plan_info *info);
 
 /* Copy the plan's bank, in natural frequency order, as complex64 [nz][L]
- * (FP32 plans: exactly the stored values; mixed plans: hi + lo widened to
- * FP32) into device memory `dst` of at least nz*L*8 bytes. For testing.    */
+ * (FP32 plans and mixed plans with FDAS_FLAG_SPLIT: exactly the stored
+ * FP32 values; other mixed plans: the 16-bit values widened to FP32) into
+ * device memory `dst` of at least nz*L*8 bytes. For testing.               */
 int fdas_plan_bank(fdas_plan_t plan, void *dst, size_t bytes, void *stream);
 
 /* The hot path: power[i*ld + r] = |B_i(r)|^2 for one spectrum.

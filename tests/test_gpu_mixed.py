@@ -177,8 +177,10 @@ def test_every_mixed_variant_odd_half(gpu, name, monkeypatch):
 
 # ---- hi + lo split products (FDAS_FLAG_SPLIT) -------------------------------
 
-@pytest.mark.parametrize("prec,tol", [("fp16", 1e-6), ("bf16", 5e-5)])
+@pytest.mark.parametrize("prec,tol", [("fp16", 1e-7), ("bf16", 1e-7)])
 def test_split_bank_matches_oracle(gpu, prec, tol):
+    """The split forms keep the bank in FP32: within FP32 rounding of the
+    oracle's FP64 bank (relative to its largest value)."""
     with gpu.Plan(100.0, 2.0, 256, 4096, prec, gpu.FLAG_SPLIT) as p:
         assert "_split" in p.info.kernel
         dev = p.bank().cpu().numpy().astype(np.complex128)
