@@ -202,9 +202,13 @@ constexpr int mix_stage_bytes() {
 }
 // Output staging: 16 blocks of 256 powers, each padded by 16 bytes.
 constexpr int kStageF = 16 * 260;
-template <bool SPLIT>
+// The skewed schedule (PF == 7, unsplit) double-buffers the stage and
+// staging buffers: Ea0, Ea1, Eb0, Eb1, then two staging buffers.
+constexpr int kSkewStageBytes = 4 * 2 * kPlane * 2;
+static_assert(kSkewStageBytes >= kMixF32, "forward buffer fits the skewed stage buffers");
+template <bool SPLIT, int PF = 0>
 constexpr int mix_smem() {
-  return mix_stage_bytes<SPLIT>() + kStageF * 4;
+  return PF == 7 ? kSkewStageBytes + 2 * kStageF * 4 : mix_stage_bytes<SPLIT>() + kStageF * 4;
 }
 // With SPLIT, X goes from the forward FFT to the lanes in FP32: 256 rows of
 // 16 values padded to 17, placed at Eb (first written by stage 1').
@@ -414,7 +418,7 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
     }
   };
   auto load_bank = [&](int iz) {
-    if constexpr (PF == 5 && !CAND) {
+    if constexpr ((PF == 5 || PF == 7) && !CAND) {
       load_bank_buf(iz);
       return;
     }
@@ -450,17 +454,34 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
                       (reinterpret_cast<uintptr_t>(power_) & 15) == 0;
   // The staged powers of the wave's TPW output blocks (one 16-byte LDS read
   // each), then their stores (or candidate offers).
-  auto read_staged = [&](f4 *v) {
+  auto read_staged_from = [&](f4 *v, const float *sg) {
 #pragma unroll
     for (int q = 0; q < TPW; ++q)
-      v[q] = *reinterpret_cast<const f4 *>(stg + 260 * (TPW * w + q) + 4 * lane);
+      v[q] = *reinterpret_cast<const f4 *>(sg + 260 * (TPW * w + q) + 4 * lane);
   };
+  auto read_staged = [&](f4 *v) { read_staged_from(v, stg); };
   // PF == 5 stores through a buffer resource that spans the segment's kept
   // outputs in plane row izr: every lane issues its 16-byte store, and a lane
   // whose group is not kept passes an offset past the resource's end, which
   // the hardware drops. That store is issued on every path (it writes nothing
   // when `none` is set or the unit takes the per-value stores), so every
   // path has at least one store after the bank row loaded before it.
+  constexpr int kPast = (int)0x80000000u;
+  // the 16-byte store's offset for each of the lane's groups (past the end
+  // unless the unit takes 16-byte stores and the group is kept), computed
+  // once per unit; through an empty asm statement, so that the store does
+  // not get split into copies under the unit's branch on vec_ok (every path
+  // must keep it, see below)
+  // (PF == 7; PF == 5 computes it at the store, which measured faster there)
+  int off4[PF == 7 ? TPW : 1];
+  if constexpr (PF == 7) {
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+      const int o0 = 256 * (TPW * w + q) + 4 * lane;
+      off4[q] = vec_ok && o0 >= half && o0 < half + U ? (o0 - half) * 4 : kPast;
+      asm volatile("" : "+v"(off4[q]));
+    }
+  }
   auto write_staged_buffer = [&](int izr, const f4 *vv, bool none) {
     const int64_t rbase = (int64_t)s * U;  // plane column of segment output `half`
     const int64_t left = nbins - rbase;
@@ -468,13 +489,17 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
         power_ + (int64_t)(izr - row_base) * ld + rbase, (short)0, nkeep * 4, 0x00020000);
     constexpr int aux = NT ? 2 : 0;  // nontemporal
-    constexpr int kPast = (int)0x80000000u;
 #pragma unroll
     for (int q = 0; q < TPW; ++q) {
       const int o0 = 256 * (TPW * w + q) + 4 * lane;
-      const bool keep4 = !none && vec_ok && o0 >= half && o0 < half + U;
-      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, vv[q]), rs,
-                                             keep4 ? (o0 - half) * 4 : kPast, 0, aux);
+      int off;
+      if constexpr (PF == 7) {
+        off = none ? kPast : off4[q];
+      } else {
+        const bool keep4 = !none && vec_ok && o0 >= half && o0 < half + U;
+        off = keep4 ? (o0 - half) * 4 : kPast;
+      }
+      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, vv[q]), rs, off, 0, aux);
       if (!vec_ok && !none) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -488,7 +513,7 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
   };
   auto write_staged = [&](int izr, const f4 *vv) {
     if (!CAND && !active) return;
-    if constexpr (PF == 5 && !CAND) {
+    if constexpr ((PF == 5 || PF == 7) && !CAND) {
       write_staged_buffer(izr, vv, false);
       return;
     }
@@ -526,7 +551,7 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
   };
 
   // ---- product + stage 2' (tiles k0 = TPW w + j; rows k1 = c; chunk h) ----
-  auto product_stage2 = [&]() {
+  auto product_stage2_to = [&](H *ea) {
     v8 av[TPW], avl[SPLIT ? TPW : 1];
 #pragma unroll
     for (int j = 0; j < TPW; ++j) {
@@ -558,37 +583,40 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
       const f4 dr = mma<H, SPLIT>(av[j], avl[SPLIT ? j : 0], K.q1[j], K.q1l[SPLIT ? j : 0]);
       const f4 di = mma<H, SPLIT>(av[j], avl[SPLIT ? j : 0], K.q2[j], K.q2l[SPLIT ? j : 0]);
       // lane holds rows k1 = 4g + i, column n2 = c
-      store_stage<H, SPLIT>(Ea, 16 * c + k0, g, dr, di);  // stage 1' butterfly (k0, n2 = c)
+      store_stage<H, SPLIT>(ea, 16 * c + k0, g, dr, di);  // stage 1' butterfly (k0, n2 = c)
     }
   };
+  auto product_stage2 = [&]() { product_stage2_to(Ea); };
   // ---- stage 1' (tiles n2 = TPW w + j; rows k0 = c) -------------------------
-  auto stage1 = [&]() {
+  auto stage1_from = [&](const H *ea, H *eb) {
 #pragma unroll
     for (int j = 0; j < TPW; ++j) {
       const int n2 = TPW * w + j;
-      const v8 a = load8<H>(Ea + (g >> 1) * kPlane, 16 * n2 + c, h);
-      const v8 al = SPLIT ? load8<H>(Ea + (2 + (g >> 1)) * kPlane, 16 * n2 + c, h) : a;
+      const v8 a = load8<H>(ea + (g >> 1) * kPlane, 16 * n2 + c, h);
+      const v8 al = SPLIT ? load8<H>(ea + (2 + (g >> 1)) * kPlane, 16 * n2 + c, h) : a;
       const f4 dr = mma<H, SPLIT>(a, al, K.p1[j], K.p1l[SPLIT ? j : 0]);
       const f4 di = mma<H, SPLIT>(a, al, K.p2[j], K.p2l[SPLIT ? j : 0]);
       // lane holds rows k0 = 4g + i, column n1 = c
-      store_stage<H, SPLIT>(Eb, 16 * c + n2, g, dr, di);  // stage 0' butterfly (n1 = c, n2)
+      store_stage<H, SPLIT>(eb, 16 * c + n2, g, dr, di);  // stage 0' butterfly (n1 = c, n2)
     }
   };
+  auto stage1 = [&]() { stage1_from(Ea, Eb); };
   // ---- stage 0' (tiles n1 = TPW w + j; rows n2 = c) + |.|^2 -> staging ----
-  auto stage0 = [&]() {
+  auto stage0_from = [&](const H *eb, float *sg) {
 #pragma unroll
     for (int j = 0; j < TPW; ++j) {
       const int n1 = TPW * w + j;
-      const v8 a = load8<H>(Eb + (g >> 1) * kPlane, 16 * n1 + c, h);
-      const v8 al = SPLIT ? load8<H>(Eb + (2 + (g >> 1)) * kPlane, 16 * n1 + c, h) : a;
+      const v8 a = load8<H>(eb + (g >> 1) * kPlane, 16 * n1 + c, h);
+      const v8 al = SPLIT ? load8<H>(eb + (2 + (g >> 1)) * kPlane, 16 * n1 + c, h) : a;
       const f4 dr = mma<H, SPLIT>(a, al, K.p1[j], K.p1l[SPLIT ? j : 0]);
       const f4 di = mma<H, SPLIT>(a, al, K.p2[j], K.p2l[SPLIT ? j : 0]);
       f4 pw;
 #pragma unroll
       for (int i = 0; i < 4; ++i) pw[i] = (dr[i] * dr[i] + di[i] * di[i]) * pscale;
-      *reinterpret_cast<f4 *>(stg + 260 * c + 16 * n1 + 4 * g) = pw;
+      *reinterpret_cast<f4 *>(sg + 260 * c + 16 * n1 + 4 * g) = pw;
     }
   };
+  auto stage0 = [&]() { stage0_from(Eb, stg); };
   // vmcnt(0), expcnt and lgkmcnt at their maxima (no wait on them)
   auto drain_vm = [&]() { __builtin_amdgcn_s_waitcnt(0x0F70); };
 
@@ -621,7 +649,74 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
   // share the counter with, so the wait for that row at the next product
   // leaves the newest template's stores outstanding: each store has until the
   // product after next, not the next one, to complete.
-  if constexpr (PF == 5 && !CAND) {
+  // PF == 7 (unsplit, one 16-wave block per CU): a skewed pipeline. Phase
+  // k runs product + stage 2' of template k, stage 1' of template k - 1,
+  // stage 0' of template k - 2 and the stores of template k - 3, then one
+  // barrier; stage and staging buffers alternate between templates (Ea and
+  // Eb of template k in buffer k & 1), so every read in a phase is of data
+  // the previous phase wrote. One barrier per template instead of two, and
+  // each wave has three independent matrix chains per phase. The memory
+  // operations are those of PF == 5 (every phase loads a bank row, clamped
+  // to the last, and issues its stores, writing nothing when there is no
+  // template k - 3).
+  if constexpr (PF == 7 && !CAND) {
+    static_assert(!SPLIT, "the skewed schedule is unsplit");
+    if (z0 < z1 && active) {
+      H *const Ea0 = reinterpret_cast<H *>(smem);
+      H *const Ea1 = Ea0 + NP * kPlane;
+      H *const Eb0 = Ea1 + NP * kPlane;
+      H *const Eb1 = Eb0 + NP * kPlane;
+      float *const sg0 = reinterpret_cast<float *>(smem + kSkewStageBytes);
+      float *const sg1 = sg0 + kStageF;
+      const int n = z1 - z0;
+      load_bank(z0);
+      f4 v[TPW];
+#pragma unroll
+      for (int q = 0; q < TPW; ++q) v[q] = __builtin_bit_cast(f4, K.q1[0]);  // any live value: nothing is written
+      write_staged_buffer(z0, v, true);
+      // phase k with compile-time parity P = k & 1; the flags say which
+      // templates exist (uniform over the block)
+      auto phase = [&](int k, auto pc, bool s2v, bool s1v, bool s0v, bool stv) {
+        constexpr int P = decltype(pc)::value;
+        H *const ea_w = P ? Ea1 : Ea0;        // stage 2' of template k
+        const H *const ea_r = P ? Ea0 : Ea1;  // stage 1' of template k - 1
+        H *const eb_w = P ? Eb0 : Eb1;
+        const H *const eb_r = P ? Eb1 : Eb0;  // stage 0' of template k - 2
+        float *const sg_w = P ? sg1 : sg0;
+        const float *const sg_r = P ? sg0 : sg1;  // stores of template k - 3
+        f4 vv[TPW];
+        read_staged_from(vv, sg_r);
+        if (s1v) stage1_from(ea_r, eb_w);
+        if (s0v) stage0_from(eb_r, sg_w);
+        if (s2v) product_stage2_to(ea_w);
+        load_bank(z0 + (k + 1 < n ? k + 1 : n - 1));
+        write_staged_buffer(stv ? z0 + k - 3 : z0, vv, !stv);
+        __syncthreads();
+      };
+      const std::integral_constant<int, 0> p0{};
+      const std::integral_constant<int, 1> p1{};
+      // fill: phases 0, 1, 2
+      phase(0, p0, true, false, false, false);
+      phase(1, p1, 1 < n, true, false, false);
+      phase(2, p0, 2 < n, 2 <= n, true, false);
+      // steady state: phases 3 .. n - 1, every part present
+      int k = 3;
+      for (; k + 1 <= n - 1; k += 2) {
+        phase(k, p1, true, true, true, true);
+        phase(k + 1, p0, true, true, true, true);
+      }
+      if (k <= n - 1) {
+        phase(k, p1, true, true, true, true);
+        ++k;
+      }
+      // drain: phases up to n + 2
+      for (; k <= n + 2; ++k) {
+        const bool s2v = k < n, s1v = k <= n, s0v = k <= n + 1;
+        if (k & 1) phase(k, p1, s2v, s1v, s0v, true);
+        else phase(k, p0, s2v, s1v, s0v, true);
+      }
+    }
+  } else if constexpr (PF == 5 && !CAND) {
     if (z0 < z1 && active) {
       load_bank(z0);
       f4 v[TPW];
@@ -675,7 +770,7 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
     for (int iz = z0; iz < z1; ++iz) {
       if (!PF) load_bank(iz);
       product_stage2();
-      if ((PF == 2 || PF == 4 || PF == 5) && iz + 1 < z1) load_bank(iz + 1);
+      if ((PF == 2 || PF >= 4) && iz + 1 < z1) load_bank(iz + 1);
       __syncthreads();
       if constexpr (PF == 2) drain_vm();
       stage1();
@@ -697,7 +792,7 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(OC
                          const c32 *__restrict__ tw, const unsigned char *__restrict__ consts,
                          float *__restrict__ power, int64_t ld, int nseg, int U, int half, int nz,
                          int zpb, int nsb, int bank_log2, CandOut cand) {
-  __shared__ __attribute__((aligned(16))) unsigned char smem[mix_smem<SPLIT>()];
+  __shared__ __attribute__((aligned(16))) unsigned char smem[mix_smem<SPLIT, PF>()];
   __shared__ float s_max[NW];
   const int sb = blockIdx.x % nsb;
   const int zg = blockIdx.x / nsb;
@@ -718,7 +813,7 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(OC
                                const H *__restrict__ bank, const c32 *__restrict__ tw,
                                const unsigned char *__restrict__ consts, int U, int half, int zpb,
                                int bank_log2) {
-  __shared__ __attribute__((aligned(16))) unsigned char smem[mix_smem<SPLIT>()];
+  __shared__ __attribute__((aligned(16))) unsigned char smem[mix_smem<SPLIT, PF>()];
   __shared__ float s_max[NW];
   const long long item = blockIdx.x;
   int lo = 0, hi = nseries - 1;
@@ -769,7 +864,7 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(OC
                                     const H *__restrict__ bank, const c32 *__restrict__ tw,
                                     const unsigned char *__restrict__ consts, int U, int half,
                                     int bank_log2) {
-  __shared__ __attribute__((aligned(16))) unsigned char smem[mix_smem<SPLIT>()];
+  __shared__ __attribute__((aligned(16))) unsigned char smem[mix_smem<SPLIT, PF>()];
   __shared__ float s_max[NW];
   __shared__ long long s_item[2];
   int par = 0;
@@ -880,6 +975,7 @@ static OlsVariant make_mixed(const char *name, int precision) {
 static const OlsVariant kMixedVariants[] = {
     // the first of each precision and split form is its default
     make_mixed<_Float16, 5, true, 16, 8, false>("fp16_L4096_mfma_w16_pfb", 1),
+    make_mixed<_Float16, 7, true, 16, 4, false>("fp16_L4096_mfma_w16_sk", 1),
     make_mixed<_Float16, 4, true, 16, 8, false>("fp16_L4096_mfma_w16_pfn", 1),
     make_mixed<_Float16, 2, true, 16, 8, false>("fp16_L4096_mfma_w16_pfw", 1),
     make_mixed<_Float16, 3, true, 16, 8, false>("fp16_L4096_mfma_w16_rot", 1),
