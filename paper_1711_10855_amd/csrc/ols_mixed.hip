@@ -6,7 +6,8 @@
 // Segment length L = 4096 = 16^3. One block of NW waves (TPW = 16 / NW tiles
 // per wave and stage) takes one segment and a group of templates:
 //   forward FFT in FP32 (radix 16, registers + LDS, as in the FP32 kernel),
-//   per-segment power-of-two scale so the largest component is in [4, 8),
+//   per-segment power-of-two scale so the largest component is in [4, 8)
+//   (FP16; BF16, with FP32's exponent range, takes a fixed scale),
 //   X rounded to 16 bits and kept in registers (the lanes' operand chunks);
 //   per template: Y = X * T' (packed 16-bit arithmetic; T' = L * T, the
 //   bank without the 1/L, stored as 16-bit planes), three inverse radix-16
@@ -111,9 +112,11 @@ template <class H>
 __device__ __forceinline__ u32x2 split2(float a, float b) {
   typedef H h2 __attribute__((ext_vector_type(2)));
   const h2 ph = {(H)a, (H)b};
-  const unsigned hi = __builtin_bit_cast(unsigned, ph);
+  unsigned hi = __builtin_bit_cast(unsigned, ph);
   float ra, rb;
   if constexpr (std::is_same<H, __bf16>::value) {
+    // (opaque, or the compiler converts a a second time for the shift)
+    asm("" : "+v"(hi));
     ra = __uint_as_float(hi << 16);
     rb = __uint_as_float(hi & 0xffff0000u);
   } else {
@@ -206,9 +209,18 @@ constexpr int kStageF = 16 * 260;
 // staging buffers: Ea0, Ea1, Eb0, Eb1, then two staging buffers.
 constexpr int kSkewStageBytes = 4 * 2 * kPlane * 2;
 static_assert(kSkewStageBytes >= kMixF32, "forward buffer fits the skewed stage buffers");
+// PF == 8 (the split form skewed the same way) doubles the stage buffers
+// and has no staging buffer: the powers go out straight from the lanes.
+template <bool SPLIT>
+constexpr int kSkewDirectBytes = 4 * (SPLIT ? 4 : 2) * kPlane * 2;
+static_assert(kSkewDirectBytes<false> >= kMixF32, "forward buffer fits");
 template <bool SPLIT, int PF = 0>
 constexpr int mix_smem() {
-  return PF == 7 ? kSkewStageBytes + 2 * kStageF * 4 : mix_stage_bytes<SPLIT>() + kStageF * 4;
+  return PF == 7   ? kSkewStageBytes + 2 * kStageF * 4
+         : PF == 8 ? (kSkewDirectBytes<SPLIT> > mix_stage_bytes<SPLIT>() + kStageF * 4
+                          ? kSkewDirectBytes<SPLIT>
+                          : mix_stage_bytes<SPLIT>() + kStageF * 4)
+                   : mix_stage_bytes<SPLIT>() + kStageF * 4;
 }
 // With SPLIT, X goes from the forward FFT to the lanes in FP32: 256 rows of
 // 16 values padded to 17, placed at Eb (first written by stage 1').
@@ -322,7 +334,7 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
   }
   // thread t now holds X[k0 + 16 k1 + 256 e] with t = 16 k0 + k1
 
-  // per-segment scale: largest component into [4, 8)
+  // per-segment scale: largest component into [4, 8) (used by FP16)
   float mx = 0.f;
 #pragma unroll
   for (int e = 0; e < 16; ++e) mx = fmaxf(mx, fmaxf(fabsf(x[e].x), fabsf(x[e].y)));
@@ -335,7 +347,10 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
   for (int k = 0; k < NW; ++k) mx = fmaxf(mx, s_max[k]);
   int ex = 0;
   if (mx > 0.f) (void)frexpf(mx, &ex);
-  const float xscale = ldexpf(1.0f, 3 - ex);
+  // BF16 has the exponent range of FP32: X is scaled by 2^-b only, so that
+  // y' = y and the power needs no scale.
+  constexpr bool kUnit = std::is_same<H, __bf16>::value;
+  const float xscale = kUnit ? ldexpf(1.0f, -bank_log2) : ldexpf(1.0f, 3 - ex);
   // power = |y'|^2 * 2^(-2 (a + b)) with a = 3 - ex, b = bank_log2
   const float pscale = ldexpf(1.0f, -2 * (3 - ex + bank_log2));
   if (fw) {
@@ -418,7 +433,7 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
     }
   };
   auto load_bank = [&](int iz) {
-    if constexpr ((PF == 5 || PF == 7) && !CAND) {
+    if constexpr ((PF == 5 || PF == 7 || PF == 8) && !CAND) {
       load_bank_buf(iz);
       return;
     }
@@ -472,12 +487,14 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
   // once per unit; through an empty asm statement, so that the store does
   // not get split into copies under the unit's branch on vec_ok (every path
   // must keep it, see below)
-  // (PF == 7; PF == 5 computes it at the store, which measured faster there)
-  int off4[PF == 7 ? TPW : 1];
-  if constexpr (PF == 7) {
+  // (PF == 7; PF == 5 computes it at the store, which measured faster there;
+  // PF == 8 stores from the stage-0' lanes, whose group of tile
+  // n1 = TPW w + q starts at output 256 c + 16 n1 + 4 g)
+  int off4[PF == 7 || PF == 8 ? TPW : 1];
+  if constexpr (PF == 7 || PF == 8) {
 #pragma unroll
     for (int q = 0; q < TPW; ++q) {
-      const int o0 = 256 * (TPW * w + q) + 4 * lane;
+      const int o0 = PF == 7 ? 256 * (TPW * w + q) + 4 * lane : 256 * c + 16 * (TPW * w + q) + 4 * g;
       off4[q] = vec_ok && o0 >= half && o0 < half + U ? (o0 - half) * 4 : kPast;
       asm volatile("" : "+v"(off4[q]));
     }
@@ -505,6 +522,33 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
         for (int i = 0; i < 4; ++i) {
           const int o = o0 + i;
           const bool keep = !none && o >= half && o < half + U && o - half < nkeep;
+          __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(vv[q][i]), rs,
+                                                keep ? (o - half) * 4 : kPast, 0, aux);
+        }
+      }
+    }
+  };
+  // (PF == 8) the powers stored by the stage-0' lanes that formed them:
+  // lane (g, c) of tile n1 holds outputs 256 c + 16 n1 + 4 g .. + 3, so one
+  // store instruction writes 16 runs of 64 bytes, and the neighbouring wave
+  // (tile n1 + 1) writes the other half of each 128-byte line.
+  auto write_direct = [&](int izr, const f4 *vv, bool none) {
+    const int64_t rbase = (int64_t)s * U;
+    const int64_t left = nbins - rbase;
+    const int nkeep = (int)(left < U ? left : U);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        power_ + (int64_t)(izr - row_base) * ld + rbase, (short)0, nkeep * 4, 0x00020000);
+    constexpr int aux = NT ? 2 : 0;  // nontemporal
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+      const int o0 = 256 * c + 16 * (TPW * w + q) + 4 * g;
+      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, vv[q]), rs,
+                                             none ? kPast : off4[q], 0, aux);
+      if (!vec_ok && !none) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int o = o0 + i;
+          const bool keep = o >= half && o < half + U && o - half < nkeep;
           __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(vv[q][i]), rs,
                                                 keep ? (o - half) * 4 : kPast, 0, aux);
         }
@@ -612,11 +656,24 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
       const f4 di = mma<H, SPLIT>(a, al, K.p2[j], K.p2l[SPLIT ? j : 0]);
       f4 pw;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) pw[i] = (dr[i] * dr[i] + di[i] * di[i]) * pscale;
+      for (int i = 0; i < 4; ++i) pw[i] = kUnit ? dr[i] * dr[i] + di[i] * di[i] : (dr[i] * dr[i] + di[i] * di[i]) * pscale;
       *reinterpret_cast<f4 *>(sg + 260 * c + 16 * n1 + 4 * g) = pw;
     }
   };
   auto stage0 = [&]() { stage0_from(Eb, stg); };
+  // (PF == 8) stage 0' with the powers kept in the lanes
+  auto stage0_pw = [&](const H *eb, f4 *pw) {
+#pragma unroll
+    for (int j = 0; j < TPW; ++j) {
+      const int n1 = TPW * w + j;
+      const v8 a = load8<H>(eb + (g >> 1) * kPlane, 16 * n1 + c, h);
+      const v8 al = SPLIT ? load8<H>(eb + (2 + (g >> 1)) * kPlane, 16 * n1 + c, h) : a;
+      const f4 dr = mma<H, SPLIT>(a, al, K.p1[j], K.p1l[SPLIT ? j : 0]);
+      const f4 di = mma<H, SPLIT>(a, al, K.p2[j], K.p2l[SPLIT ? j : 0]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) pw[j][i] = kUnit ? dr[i] * dr[i] + di[i] * di[i] : (dr[i] * dr[i] + di[i] * di[i]) * pscale;
+    }
+  };
   // vmcnt(0), expcnt and lgkmcnt at their maxima (no wait on them)
   auto drain_vm = [&]() { __builtin_amdgcn_s_waitcnt(0x0F70); };
 
@@ -714,6 +771,65 @@ __device__ __forceinline__ void mixed_unit(const unsigned char *__restrict__ con
         const bool s2v = k < n, s1v = k <= n, s0v = k <= n + 1;
         if (k & 1) phase(k, p1, s2v, s1v, s0v, true);
         else phase(k, p0, s2v, s1v, s0v, true);
+      }
+    }
+  } else if constexpr (PF == 8 && !CAND) {
+    // PF == 8: the skewed pipeline of PF == 7 without the staging buffer
+    // (stage 0' of template k - 2 stores its powers in the same phase), so
+    // that the doubled stage buffers of the split form fit in LDS. Every
+    // phase loads a bank row and then issues one store per tile (writing
+    // nothing while there is no template k - 2), so the wait for that row at
+    // the next product leaves the stores in flight.
+    if (z0 < z1 && active) {
+      H *const Ea0 = reinterpret_cast<H *>(smem);
+      H *const Ea1 = Ea0 + NP * kPlane;
+      H *const Eb0 = Ea1 + NP * kPlane;
+      H *const Eb1 = Eb0 + NP * kPlane;
+      const int n = z1 - z0;
+      load_bank(z0);
+      f4 v0[TPW];
+#pragma unroll
+      for (int q = 0; q < TPW; ++q) v0[q] = __builtin_bit_cast(f4, K.q1[0]);  // any live value: nothing is written
+      write_direct(z0, v0, true);
+      auto phase = [&](int k, auto pc, bool s2v, bool s1v, bool s0v) {
+        constexpr int P = decltype(pc)::value;
+        H *const ea_w = P ? Ea1 : Ea0;        // stage 2' of template k
+        const H *const ea_r = P ? Ea0 : Ea1;  // stage 1' of template k - 1
+        H *const eb_w = P ? Eb0 : Eb1;
+        const H *const eb_r = P ? Eb1 : Eb0;  // stage 0' of template k - 2
+        f4 vv[TPW];
+        if (s1v) stage1_from(ea_r, eb_w);
+        if (s0v) {
+          stage0_pw(eb_r, vv);
+        } else {
+#pragma unroll
+          for (int q = 0; q < TPW; ++q) vv[q] = __builtin_bit_cast(f4, K.q1[0]);
+        }
+        if (s2v) product_stage2_to(ea_w);
+        load_bank(z0 + (k + 1 < n ? k + 1 : n - 1));
+        write_direct(s0v ? z0 + k - 2 : z0, vv, !s0v);
+        __syncthreads();
+      };
+      const std::integral_constant<int, 0> p0{};
+      const std::integral_constant<int, 1> p1{};
+      // fill: phases 0, 1
+      phase(0, p0, true, false, false);
+      phase(1, p1, 1 < n, true, false);
+      // steady state: phases 2 .. n - 1, every part present
+      int k = 2;
+      for (; k + 1 <= n - 1; k += 2) {
+        phase(k, p0, true, true, true);
+        phase(k + 1, p1, true, true, true);
+      }
+      if (k <= n - 1) {
+        phase(k, p0, true, true, true);
+        ++k;
+      }
+      // drain: phases up to n + 1
+      for (; k <= n + 1; ++k) {
+        const bool s2v = k < n, s1v = k <= n;
+        if (k & 1) phase(k, p1, s2v, s1v, true);
+        else phase(k, p0, s2v, s1v, true);
       }
     }
   } else if constexpr (PF == 5 && !CAND) {
@@ -988,7 +1104,9 @@ static const OlsVariant kMixedVariants[] = {
     // hi + lo split products (FDAS_FLAG_SPLIT)
     make_mixed<_Float16, 5, true, 16, 4, true>("fp16_L4096_mfma_split_w16_pfb", 1),
     make_mixed<_Float16, 2, true, 16, 4, true>("fp16_L4096_mfma_split_w16_pfw", 1),
+    make_mixed<_Float16, 8, true, 16, 4, true>("fp16_L4096_mfma_split_w16_sk", 1),
     make_mixed<__bf16, 5, true, 16, 4, true>("bf16_L4096_mfma_split_w16_pfb", 2),
+    make_mixed<__bf16, 8, true, 16, 4, true>("bf16_L4096_mfma_split_w16_sk", 2),
     make_mixed<__bf16, 2, true, 16, 4, true>("bf16_L4096_mfma_split_w16_pfw", 2),
     make_mixed<__bf16, 4, true, 16, 4, true>("bf16_L4096_mfma_split_w16_pfn", 2),
     make_mixed<__bf16, 3, true, 16, 4, true>("bf16_L4096_mfma_split_w16_rot", 2),
