@@ -239,3 +239,27 @@ def test_split_batch_matches_oracle(gpu):
         print(f"bf16 split batch nbins={n} zmax={z}: {err:.3e}")
         assert err <= TOL_MIXED
         assert np.all(o[:, n:] == -5.0)
+
+
+@pytest.mark.parametrize("prec,split", [("bf16", True), ("bf16", False), ("fp16", True)])
+def test_zero_and_scaled_inputs_other_forms(gpu, prec, split):
+    """Zero input gives a zero plane; a power-of-two input scale scales the
+    powers exactly (FP16 through its per-segment scale, BF16 at 4096 points
+    through its fixed one, exact while no value leaves FP32's normal range);
+    inputs of magnitude 1e-12 and 1e+12 stay within the bar."""
+    flags = gpu.FLAG_SPLIT if split else 0
+    tol = TOL_MIXED if (prec == "fp16" or split) else 2e-2
+    import torch
+    z = torch.zeros(9000, dtype=torch.complex64, device="cuda")
+    out = gpu.convolve(z, 10.0, 2.0, 256, 4096, prec, flags)
+    assert float(out.abs().max()) == 0.0
+    a = synth.small_random_spectrum(9000, seed=6)
+    p1 = gpu.convolve(to_dev(a), 10.0, 2.0, 256, 4096, prec, flags).cpu().numpy()
+    p2 = gpu.convolve(to_dev(a * 1024.0), 10.0, 2.0, 256, 4096, prec, flags).cpu().numpy()
+    assert np.array_equal(p1 * (1024.0 ** 2), p2)
+    for s in (1e-12, 1e12):
+        p3 = gpu.convolve(to_dev(a * s), 10.0, 2.0, 256, 4096, prec, flags).cpu().numpy()
+        ref = oracle.plane_direct(a.astype(np.complex128) * s, 10.0, 2.0, 256)
+        err = rel_err(p3, ref)
+        print(f"{prec} split={split} scale {s:g}: {err:.3e}")
+        assert err <= tol
